@@ -1,0 +1,232 @@
+/*
+ * s3a: dense confidence-weighted Sim(3) alignment of submap pointmaps, its
+ * cost adjoint, and the Sim(3) pose-graph solve, on one AMD Instinct MI355X
+ * (gfx950). C ABI: plain pointers and sizes only.
+ *
+ * The problem statement follows EC3R-SLAM (arXiv 2510.02080):
+ *   - Sec. III-C.2, eq. (sim3): given corresponding points P = {p_i} (current
+ *     submap) and Q = {q_i} (another submap, same pixels of a shared keyframe)
+ *     and confidence-derived weights w_i, find S = {s, R, t} in Sim(3)
+ *     minimising sum_i w_i |s R p_i + t - q_i|^2, solved by the weighted
+ *     Umeyama closed form; S becomes a relative Sim(3) edge of the pose graph.
+ *   - Sec. III-E: nodes T_t in Sim(3), edge residual
+ *     e_ij = Log(T_ij^{-1} T_i^{-1} T_j), energy sum e_ij^T Omega_ij e_ij,
+ *     poses initialised by chaining the relative transforms.
+ *
+ * This library refines the closed-form start with Huber IRLS: K Gauss-Newton
+ * steps on sum_i w_i rho_delta(|S p_i - q_i|), each reducing per-point
+ * residuals and Jacobians to 7x7 normal equations (solved in FP64).
+ *
+ * Conventions
+ *   - A similarity {s, R, t} maps x -> s R x + t. R is row-major.
+ *   - Tangent vectors xi = (rho[3], omega[3], sigma): translation, rotation,
+ *     log-scale; perturbations act on the left: S' = Exp(xi) S.
+ *   - Mask and weights: point i of a pair is valid iff p_i, q_i, c_i are all
+ *     finite and c_i >= conf_threshold; w_i = m_i c_i / C, C = sum m_j c_j.
+ *
+ * Memory and streams
+ *   - "device" pointers are HIP device memory on the handle's device; "host"
+ *     pointers are ordinary host memory. The caller owns every array passed
+ *     in; the library keeps no pointer past the call.
+ *   - Calls enqueue work on the given stream (a hipStream_t; NULL = the null
+ *     stream) and return; device outputs are valid once the stream has
+ *     reached that point. Calls that say they synchronise do so on that
+ *     stream before returning.
+ *   - A handle owns its workspace (grown on demand), captured graphs and
+ *     autotuning results. A handle must not be used by two threads at once.
+ *
+ * Errors
+ *   - Every call returns S3A_OK (0) or a negative code (s3a_strerror).
+ *     S3A_EINVAL: a bad argument (null pointer, negative count, unknown dtype,
+ *     delta <= 0 or NaN, tau < 0 or NaN, iters < 0, misaligned plane).
+ *     S3A_EHIP: a HIP runtime error (code kept, s3a_last_hip_error).
+ *     S3A_ENOMEM: workspace allocation failed.
+ *   - Problems of one pair do not fail the call: they are reported in that
+ *     pair's status (S3A_PAIR_*), and the pair's outputs are the identity with
+ *     cost NaN. Other pairs are unaffected.
+ */
+#ifndef S3A_H
+#define S3A_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct s3a_handle s3a_handle;
+typedef void* s3a_stream; /* hipStream_t */
+
+/* Similarity x -> s R x + t; 128 bytes, FP64. */
+typedef struct {
+  double R[9]; /* row-major rotation */
+  double t[3];
+  double s; /* > 0 */
+  double pad[3];
+} s3a_sim3;
+
+enum { S3A_F32 = 0, S3A_BF16 = 1 };
+
+enum { S3A_OK = 0, S3A_EINVAL = -1, S3A_EHIP = -2, S3A_ENOMEM = -3 };
+
+/* Per-pair status. */
+enum {
+  S3A_PAIR_OK = 0,
+  S3A_PAIR_EMPTY = 1,      /* no valid point (or all weights zero with tau = 0) */
+  S3A_PAIR_DEGENERATE = 2, /* coincident or collinear points, or a non-SPD normal matrix */
+  S3A_PAIR_NONFINITE = 3,  /* no valid point and some were dropped for NaN/Inf, or a non-finite solve */
+  S3A_PAIR_BADRANGE = 4    /* offsets[k] > offsets[k+1], or outside [0, n_points] */
+};
+
+/* Flags of s3a_align_desc.flags. */
+#define S3A_FLAG_PLAIN 0x1u        /* one pair at a time, one launch per pass */
+#define S3A_FLAG_FINAL_COST 0x2u   /* one more pass: cost and inliers at the final iterate */
+#define S3A_FLAG_NO_GRAPH 0x4u     /* batched: launch directly, do not capture/replay a graph */
+#define S3A_FLAG_MULTI_LAUNCH 0x8u /* batched: one launch per pass instead of one persistent launch */
+
+/*
+ * A batch of pairs in structure-of-arrays form: seven planes (px, py, pz,
+ * qx, qy, qz, conf) of n_points elements each, all of one dtype (FP32, or
+ * BF16 bit patterns as uint16), in device memory, each 16-byte aligned.
+ * Pair k owns elements [offsets[k], offsets[k+1]).
+ */
+typedef struct {
+  int32_t dtype;          /* S3A_F32 or S3A_BF16 */
+  int32_t n_pairs;        /* >= 0 */
+  int64_t n_points;       /* elements per plane, >= 0 */
+  const int64_t* offsets; /* device, n_pairs + 1 entries */
+  const void* px;
+  const void* py;
+  const void* pz; /* source points P (current submap) */
+  const void* qx;
+  const void* qy;
+  const void* qz; /* target points Q (other submap) */
+  const void* conf;     /* per-correspondence confidence */
+  float conf_threshold; /* tau >= 0; valid iff conf >= tau */
+  int32_t irls_iters;   /* K >= 0 Gauss-Newton steps after the closed form */
+  double huber_delta;   /* delta > 0 (metres in the target frame); +inf = least squares */
+  uint32_t flags;       /* S3A_FLAG_* */
+  int32_t reserved;     /* 0 */
+} s3a_align_desc;
+
+/* Per-pair diagnostics of s3a_align_pairs (device array of n_pairs). */
+typedef struct {
+  double cost;       /* L at the last linearisation point S_{K-1}; NaN if K = 0 or failed */
+  double final_cost; /* L at S_K with S3A_FLAG_FINAL_COST, else NaN */
+  double weight_sum; /* C = sum m_i c_i */
+  double H[28];      /* upper triangle (row-major) of the last Gauss-Newton matrix, normalised weights */
+  double g[7];       /* and its gradient: L's derivative w.r.t. xi at S_{K-1} */
+  int64_t n_valid;   /* V = number of valid points */
+  int64_t n_nonfinite;  /* points dropped for a NaN/Inf value */
+  int64_t n_inliers;    /* valid points with residual <= delta at S_{K-1} */
+  int64_t final_inliers;/* the same at S_K (with S3A_FLAG_FINAL_COST) */
+  int32_t status;       /* S3A_PAIR_* */
+  int32_t iters;        /* Gauss-Newton steps taken */
+} s3a_align_info;
+
+int s3a_create(s3a_handle** out, int device);
+int s3a_destroy(s3a_handle* h);
+
+/*
+ * Align every pair of a batch (Sec. III-C.2, eq. (sim3), refined by Huber IRLS).
+ *   init:   device, n_pairs similarities used instead of the closed-form start,
+ *           or NULL for the weighted Umeyama closed form.
+ *   S_out:  device, n_pairs results (the K-th Gauss-Newton iterate).
+ *   info:   device, n_pairs diagnostics, or NULL.
+ * Batched (default): all pairs together, one persistent launch captured in a
+ * graph and replayed on later calls of the same shape. S3A_FLAG_PLAIN: one
+ * pair at a time, one launch per pass; synchronises the stream once to read
+ * the pair sizes.
+ */
+int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* init,
+                    s3a_sim3* S_out, s3a_align_info* info, s3a_stream stream);
+
+/*
+ * Forward of the differentiable alignment cost, per pair:
+ *   L_k = sum_i w_i rho_delta(|S'_k p_i - q_i|),  S'_k = Exp(xi_k) S_k,
+ * the Huber form of eq. (sim3).
+ *   S:  device, n_pairs; xi: device, 7 * n_pairs doubles, or NULL (xi = 0).
+ *   L_out, C_out: device, n_pairs doubles (C = sum m_i c_i; L = NaN if C = 0).
+ */
+int s3a_align_cost(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* S, const double* xi,
+                   double* L_out, double* C_out, s3a_stream stream);
+
+/*
+ * Adjoint of s3a_align_cost: given gL_k = d(loss)/dL_k, writes
+ *   dL/dq_i = -w_i psi_i r_i,  dL/dp_i = w_i psi_i (s'R')^T r_i,
+ *   dL/dc_i = m_i (rho_i - L) / C,  dL/dxi = J_l(xi)^T sum_i w_i psi_i J_i^T r_i,
+ * each scaled by gL_k (r_i = S' p_i - q_i, psi_i = rho'(e_i)/e_i, J_i = [I, -[y_i]x, y_i]).
+ * Huber weights are recomputed, not stored. L and C are the forward's outputs.
+ *   gpx..gqz, gc: device FP32 arrays of n_points (NULL = not wanted); entries
+ *                 outside every pair's range are left untouched.
+ *   gxi: device, 7 * n_pairs doubles, or NULL.
+ */
+int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* S,
+                             const double* xi, const double* L, const double* C, const double* gL,
+                             float* gpx, float* gpy, float* gpz, float* gqx, float* gqy, float* gqz,
+                             float* gc, double* gxi, s3a_stream stream);
+
+/* Pose-graph options. */
+#define S3A_PGO_INIT_CHAIN 0x1u /* ignore T on input: chain the edges from the gauge node */
+
+typedef struct {
+  int32_t iters;      /* Gauss-Newton iterations (20) */
+  int32_t gauge;      /* node held fixed (0) */
+  double huber_delta; /* Huber threshold on sqrt(e^T Omega e); +inf = none */
+  double lambda;      /* Levenberg damping: H + lambda diag(H); 0 = Gauss-Newton */
+  uint32_t flags;     /* S3A_PGO_* */
+  int32_t reserved;
+} s3a_pgo_params;
+
+typedef struct {
+  double chi2[64];        /* sum e^T Omega e at each linearisation point (first 64) */
+  double final_chi2;      /* at the returned poses */
+  int32_t iters;          /* iterations run */
+  int32_t status;         /* 0 ok, 2 factorisation failed (graph not connected to the gauge) */
+  int64_t factor_nnz_blocks; /* 7x7 blocks in the Cholesky factor (after fill) */
+} s3a_pgo_report;
+
+/*
+ * Sim(3) pose-graph optimisation (Sec. III-E), Gauss-Newton with Huber edge
+ * weights and a 7x7-block sparse Cholesky factorisation in FP64 on the GPU.
+ *   ij:     host, 2 * n_edges node indices (i, j) per edge; T_ij maps frame j to
+ *           frame i, so a consistent graph has T_j = T_i T_ij.
+ *   T_meas: device, n_edges relative similarities T_ij.
+ *   omega:  device, 49 * n_edges row-major information matrices, or NULL (I).
+ *   T:      device, n_nodes poses; initial values on input (unless
+ *           S3A_PGO_INIT_CHAIN), optimised poses on output.
+ *   report: host, or NULL.
+ * Synchronises the stream (the report is host memory).
+ */
+int s3a_pose_graph_solve(s3a_handle* h, int32_t n_nodes, int32_t n_edges, const int32_t* ij,
+                         const s3a_sim3* T_meas, const double* omega, s3a_sim3* T,
+                         const s3a_pgo_params* params, s3a_pgo_report* report, s3a_stream stream);
+
+/*
+ * Launch shape of the alignment kernels. The autotuner picks one per
+ * (dtype, batch size class) by timing candidates on the caller's data;
+ * s3a_set_tuning forces one (for tests and sweeps).
+ */
+typedef struct {
+  int32_t wg;       /* workgroup size: 256 or 512 */
+  int32_t items;    /* vector loads per thread per tile: 2, 4 or 8 */
+  int32_t occupancy;/* persistent workgroups per compute unit: 1..8 */
+  int32_t window;   /* pairs per scheduling window in the persistent launch (0 = all) */
+} s3a_tuning;
+
+/* Time candidate launch shapes on this batch and keep the fastest for its
+ * (dtype, size class). Synchronises the stream. best may be NULL. */
+int s3a_autotune(s3a_handle* h, const s3a_align_desc* desc, s3a_tuning* best, s3a_stream stream);
+int s3a_set_tuning(s3a_handle* h, int32_t dtype, const s3a_tuning* t); /* t = NULL: back to automatic */
+int s3a_get_tuning(s3a_handle* h, int32_t dtype, int64_t n_points, s3a_tuning* t);
+
+const char* s3a_strerror(int code);
+int s3a_last_hip_error(const s3a_handle* h);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int s3a_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* S3A_H */

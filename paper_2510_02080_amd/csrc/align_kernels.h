@@ -1,0 +1,250 @@
+// Point passes of the dense Sim(3) alignment, its cost and its adjoint.
+//
+// One pass streams the seven SoA planes of every pair once and reduces
+// per-point terms to NSTAT values per tile (see s3a_internal.h for the
+// layout). Reads are 16-byte vectors (4 FP32 or 8 BF16 elements per plane per
+// load), consecutive lanes on consecutive vectors. A tile is WG * ITEMS
+// vectors of one pair; its reduction goes lane -> wavefront (butterfly) ->
+// workgroup (LDS, FP64) -> one FP64 partial per tile. Per-pair totals are
+// summed later over the pair's tiles in a fixed order, so results are
+// bitwise reproducible run to run.
+#pragma once
+
+#include <type_traits>
+
+#include "s3a_internal.h"
+
+namespace s3a {
+
+// ---------------------------------------------------------------- loads
+
+template <int DT>
+struct Planes;
+
+template <>
+struct Planes<S3A_F32> {
+  static constexpr int VEC = 4;
+  __device__ static inline void load(const void* const* pl, int64_t g0, int64_t n, float (&v)[7][4]) {
+    if (g0 + 4 <= n) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const float4 x = *reinterpret_cast<const float4*>(static_cast<const float*>(pl[j]) + g0);
+        v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          v[j][e] = (g0 + e < n) ? static_cast<const float*>(pl[j])[g0 + e] : 0.0f;
+    }
+  }
+};
+
+template <>
+struct Planes<S3A_BF16> {
+  static constexpr int VEC = 8;
+  __device__ static inline float lo(uint32_t u) { return __uint_as_float(u << 16); }
+  __device__ static inline float hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
+  __device__ static inline void load(const void* const* pl, int64_t g0, int64_t n, float (&v)[7][8]) {
+    if (g0 + 8 <= n) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j) {
+        const uint4 x = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(pl[j]) + g0);
+        v[j][0] = lo(x.x); v[j][1] = hi(x.x); v[j][2] = lo(x.y); v[j][3] = hi(x.y);
+        v[j][4] = lo(x.z); v[j][5] = hi(x.z); v[j][6] = lo(x.w); v[j][7] = hi(x.w);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          v[j][e] = (g0 + e < n) ? lo(static_cast<const uint16_t*>(pl[j])[g0 + e]) : 0.0f;
+    }
+  }
+};
+
+__device__ inline bool finite7(const float* x) {
+  bool f = true;
+#pragma unroll
+  for (int j = 0; j < 7; ++j) f = f && __builtin_isfinite(x[j]);
+  return f;
+}
+
+// ---------------------------------------------------------------- per-point terms
+
+// Closed-form start: weighted raw moments, accumulated in FP64 (the products
+// of FP32 inputs are exact or nearly so in FP64).
+__device__ inline void point_moments(double (&a)[NSTAT], const float* x, bool in, float tau) {
+  const bool fin = finite7(x);
+  const bool valid = in && fin && x[6] >= tau;
+  const double w = valid ? (double)x[6] : 0.0;
+  const double p0 = valid ? (double)x[0] : 0.0, p1 = valid ? (double)x[1] : 0.0, p2 = valid ? (double)x[2] : 0.0;
+  const double q0 = valid ? (double)x[3] : 0.0, q1 = valid ? (double)x[4] : 0.0, q2 = valid ? (double)x[5] : 0.0;
+  const double wp0 = w * p0, wp1 = w * p1, wp2 = w * p2;
+  const double wq0 = w * q0, wq1 = w * q1, wq2 = w * q2;
+  a[0] += w;
+  a[1] += wp0; a[2] += wp1; a[3] += wp2;
+  a[4] += wq0; a[5] += wq1; a[6] += wq2;
+  a[7] = fma(wp0, p0, fma(wp1, p1, fma(wp2, p2, a[7])));
+  a[8] = fma(wq0, p0, a[8]);  a[9] = fma(wq0, p1, a[9]);  a[10] = fma(wq0, p2, a[10]);
+  a[11] = fma(wq1, p0, a[11]); a[12] = fma(wq1, p1, a[12]); a[13] = fma(wq1, p2, a[13]);
+  a[14] = fma(wq2, p0, a[14]); a[15] = fma(wq2, p1, a[15]); a[16] = fma(wq2, p2, a[16]);
+  a[17] += valid ? 1.0 : 0.0;
+  a[18] += (in && !fin) ? 1.0 : 0.0;
+}
+
+// Residual r = s R p + t - q and centred model point y_c = s R p + t - c,
+// formed in FP64 (so that r keeps full FP32 relative precision however far
+// the points are from the origin), then rounded to FP32.
+__device__ inline void residual(const PointParams& P, const float* x, float (&r)[3], float (&yc)[3]) {
+  const double p0 = x[0], p1 = x[1], p2 = x[2];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    const double y = fma(P.M[3 * i], p0, fma(P.M[3 * i + 1], p1, fma(P.M[3 * i + 2], p2, P.t[i])));
+    r[i] = (float)(y - (double)x[3 + i]);
+    yc[i] = (float)(y - P.c[i]);
+  }
+}
+
+// One Gauss-Newton point (IRLS weight recomputed at the current iterate).
+// Accumulated in FP32 over the few points a lane handles per tile; the
+// butterfly and everything above it are pairwise, FP64 from the workgroup up.
+__device__ inline void point_gn(float (&a)[NSTAT], const PointParams& P, float* x, bool in, float tau,
+                                float delta) {
+  const bool valid = in && finite7(x) && x[6] >= tau;
+  if (!valid) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) x[j] = 0.0f;
+  }
+  float r[3], y[3];
+  residual(P, x, r, y);
+  const float e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  const bool inl = e2 <= delta * delta;
+  float psi, rho;
+  if (inl) {
+    psi = 1.0f;
+    rho = 0.5f * e2;
+  } else {
+    const float ie = rsqrtf(e2);
+    psi = delta * ie;
+    rho = delta * (e2 * ie - 0.5f * delta);
+  }
+  const float w = x[6];  // zero when invalid
+  const float om = w * psi;
+  const float oy0 = om * y[0], oy1 = om * y[1], oy2 = om * y[2];
+  a[0] += om;
+  a[1] += oy0; a[2] += oy1; a[3] += oy2;
+  a[4] = fmaf(oy0, y[0], a[4]); a[5] = fmaf(oy0, y[1], a[5]); a[6] = fmaf(oy0, y[2], a[6]);
+  a[7] = fmaf(oy1, y[1], a[7]); a[8] = fmaf(oy1, y[2], a[8]); a[9] = fmaf(oy2, y[2], a[9]);
+  a[10] = fmaf(om, r[0], a[10]); a[11] = fmaf(om, r[1], a[11]); a[12] = fmaf(om, r[2], a[12]);
+  a[13] += oy1 * r[2] - oy2 * r[1];
+  a[14] += oy2 * r[0] - oy0 * r[2];
+  a[15] += oy0 * r[1] - oy1 * r[0];
+  a[16] = fmaf(oy0, r[0], fmaf(oy1, r[1], fmaf(oy2, r[2], a[16])));
+  a[17] = fmaf(w, rho, a[17]);
+  a[18] += (valid && inl) ? 1.0f : 0.0f;
+}
+
+// Cost at S: 0 sum w, 1 sum w rho, 2 V (FP64 per lane).
+__device__ inline void point_cost(double (&a)[NSTAT], const PointParams& P, float* x, bool in, float tau,
+                                  float delta) {
+  const bool valid = in && finite7(x) && x[6] >= tau;
+  if (!valid) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) x[j] = 0.0f;
+  }
+  float r[3], y[3];
+  residual(P, x, r, y);
+  const float e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+  float rho;
+  if (e2 <= delta * delta) rho = 0.5f * e2;
+  else rho = delta * (e2 * rsqrtf(e2) - 0.5f * delta);
+  a[0] += (double)x[6];
+  a[1] = fma((double)x[6], (double)rho, a[1]);
+  a[2] += valid ? 1.0 : 0.0;
+}
+
+// ---------------------------------------------------------------- reductions
+
+template <typename T>
+__device__ inline T wave_sum(T v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Reduce NSTAT per-lane values over the workgroup and store one FP64 partial.
+template <typename T, int WG>
+__device__ inline void block_store(T (&acc)[NSTAT], double (*red)[NSTAT], double* out, int nstat) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) {
+    if (j < nstat) {
+      const T v = wave_sum(acc[j]);
+      if (lane == 0) red[wv][j] = (double)v;
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < nstat) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < WG / 64; ++q) s += red[q][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- tile bodies
+
+template <int DT, int MODE, int WG, int ITEMS>
+__device__ inline void tile_body(const Shape& sh, const void* const* pl, const TileDesc& td,
+                                 const PointParams& P, double (*red)[NSTAT], double* out) {
+  constexpr int VEC = Planes<DT>::VEC;
+  using Acc = typename std::conditional<MODE == MODE_GN, float, double>::type;
+  Acc acc[NSTAT];
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) acc[j] = Acc(0);
+  const bool run = (MODE == MODE_MOMENTS) || P.active;
+  if (run) {
+#pragma unroll 1
+    for (int it = 0; it < ITEMS; ++it) {
+      const int64_t g0 = td.begin + (int64_t)(it * WG + (int)threadIdx.x) * VEC;
+      if (g0 < td.end) {
+        float v[7][VEC];
+        Planes<DT>::load(pl, g0, sh.n_points, v);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const int64_t g = g0 + e;
+          const bool in = (g >= td.lo) && (g < td.end);
+          float x[7];
+#pragma unroll
+          for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+          if constexpr (MODE == MODE_MOMENTS) point_moments(acc, x, in, sh.tau);
+          else if constexpr (MODE == MODE_GN) point_gn(acc, P, x, in, sh.tau, sh.delta_f);
+          else point_cost(acc, P, x, in, sh.tau, sh.delta_f);
+        }
+      }
+    }
+  }
+  const int nstat = (MODE == MODE_COST) ? 3 : NSTAT;
+  block_store<Acc, WG>(acc, red, out, nstat);
+}
+
+// Sum the pair's tile partials in a fixed order (lane-strided, then a fixed
+// butterfly): the same value on every run.
+__device__ inline void pair_sums(const Work& w, const PairSched& sc, int nstat, double (&s)[NSTAT]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) s[j] = 0.0;
+  for (int t = sc.tile0 + lane; t < sc.tile0 + sc.ntiles; t += 64) {
+    const double* p = w.partials + (int64_t)t * NSTAT;
+#pragma unroll
+    for (int j = 0; j < NSTAT; ++j)
+      if (j < nstat) s[j] += p[j];
+  }
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) s[j] = wave_sum(s[j]);
+}
+
+}  // namespace s3a

@@ -1,0 +1,118 @@
+// Internal device-side data structures of the s3a library.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "s3a.h"
+#include "dmath.h"
+
+namespace s3a {
+
+// Statistics reduced per tile and per pair. Every point pass reduces NSTAT
+// values: the alignment passes the 17 sufficient statistics of the Umeyama or
+// Gauss-Newton system plus two counters, the cost pass 3, the adjoint pass 7.
+constexpr int NSTAT = 19;
+
+// Moments pass (closed-form start), weights w = m c:
+//   0 W, 1-3 sum w p, 4-6 sum w q, 7 sum w |p|^2, 8-16 sum w q_a p_b,
+//   17 valid count V, 18 non-finite count.
+// Gauss-Newton pass at S, centre c, y_c = S p - c, r = S p - q, om = w psi:
+//   0 sum om, 1-3 sum om y_c, 4-9 sum om y_c y_c^T (xx xy xz yy yz zz),
+//   10-12 sum om r, 13-15 sum om y_c x r, 16 sum om y_c . r,
+//   17 sum w rho, 18 inlier count.
+enum PassMode { MODE_MOMENTS = 0, MODE_GN = 1, MODE_COST = 2, MODE_ADJOINT = 3 };
+
+// Tile boundaries are multiples of 8 elements so that 16-byte vector loads of
+// FP32 (4 elements) and BF16 (8 elements) planes are aligned.
+constexpr int64_t TILE_ALIGN = 8;
+
+struct TileDesc {
+  int64_t begin;  // first element loaded (multiple of TILE_ALIGN)
+  int64_t end;    // one past the last element of this tile
+  int64_t lo;     // first element of the pair (elements in [begin, lo) are masked)
+  int32_t pair;
+  int32_t pad;
+};
+
+struct PairSched {
+  int64_t a, b;     // element range of the pair
+  int32_t tile0;    // first tile
+  int32_t ntiles;   // >= 1 (an empty or bad pair gets one empty tile)
+  int32_t bad;      // offsets out of order or out of range
+  int32_t pad;
+};
+
+// Per-pair parameters read by the point passes.
+struct PointParams {
+  double M[9];   // s R (FP64), y = M p + t
+  double t[3];
+  double c[3];   // centre of the Gauss-Newton statistics
+  float Mf[9];   // s R (FP32), for gradients w.r.t. p
+  float inv_C;   // 1 / C (adjoint)
+  float scale;   // gL (adjoint)
+  float L;       // cost (adjoint)
+  int32_t active;// 0: skip (pair failed or finished)
+  int32_t pad;
+};
+
+// FP64 master state per pair.
+struct PairState {
+  Sim3d S;
+  double C;
+  double cq[3];
+  double cost_lin;
+  double H[28];
+  double g[7];
+  int64_t V;
+  int64_t nnf;
+  int64_t inl_lin;
+  int32_t status;
+  int32_t iters;
+};
+
+// Per-call pointers read by every kernel of a call.
+struct CallDesc {
+  const void* planes[7];
+  const int64_t* offsets;
+  const s3a_sim3* init;  // or null
+  s3a_sim3* S_out;
+  s3a_align_info* info;
+  // cost / adjoint
+  const s3a_sim3* S_in;
+  const double* xi;
+  const double* L_in;
+  const double* C_in;
+  const double* gL;
+  double* L_out;
+  double* C_out;
+  float* grad[7];
+  double* gxi;
+};
+
+// Shape of a call (passed by value).
+struct Shape {
+  int64_t n_points;
+  int32_t n_pairs;
+  int32_t K;
+  float tau;
+  float delta_f;
+  double delta;
+  uint32_t flags;
+  int32_t tile_elems;
+};
+
+// Workspace pointers (device).
+struct Work {
+  TileDesc* tiles;
+  PairSched* sched;
+  PointParams* params;
+  PairState* state;
+  double* partials;    // [max_tiles][NSTAT]
+  int32_t* total_tiles;
+  uint32_t* counters;  // [n_pairs] arrivals, then 4 scheduling words
+  uint32_t* flags;     // [n_pairs] per-pair published pass (persistent launch)
+  int32_t* scan_tmp;
+};
+
+}  // namespace s3a
