@@ -75,7 +75,8 @@ enum {
   S3A_PAIR_EMPTY = 1,      /* no valid point (or all weights zero with tau = 0) */
   S3A_PAIR_DEGENERATE = 2, /* coincident or collinear points, or a non-SPD normal matrix */
   S3A_PAIR_NONFINITE = 3,  /* no valid point and some were dropped for NaN/Inf, or a non-finite solve */
-  S3A_PAIR_BADRANGE = 4    /* offsets[k] > offsets[k+1], or outside [0, n_points] */
+  S3A_PAIR_BADRANGE = 4,   /* offsets[k] > offsets[k+1], or outside [0, n_points] */
+  S3A_PAIR_ABORTED = 5     /* the batched launch stopped waiting for this pair (internal error) */
 };
 
 /* Flags of s3a_align_desc.flags. */
@@ -219,6 +220,18 @@ typedef struct {
 int s3a_autotune(s3a_handle* h, const s3a_align_desc* desc, s3a_tuning* best, s3a_stream stream);
 int s3a_set_tuning(s3a_handle* h, int32_t dtype, const s3a_tuning* t); /* t = NULL: back to automatic */
 int s3a_get_tuning(s3a_handle* h, int32_t dtype, int64_t n_points, s3a_tuning* t);
+
+/*
+ * Kernel timing (profiling aid). While on, calls launch directly (no graph
+ * replay) and record HIP events on the caller's stream around every launch of
+ * the call's dominant point kernel: the persistent kernel of a batched call,
+ * the pass kernels of a plain or multi-launch call, the adjoint kernel of a
+ * backward call, the cost kernel of a cost call. s3a_kernel_time synchronises
+ * on those events and returns their summed duration (ms) and launch count
+ * since the previous s3a_kernel_time, then clears them.
+ */
+int s3a_set_timing(s3a_handle* h, int on);
+int s3a_kernel_time(s3a_handle* h, double* ms, int32_t* launches);
 
 const char* s3a_strerror(int code);
 int s3a_last_hip_error(const s3a_handle* h);

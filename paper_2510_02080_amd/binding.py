@@ -13,7 +13,7 @@ LIB_PATH = os.path.join(HERE, "libs3a.so")
 
 F32, BF16 = 0, 1
 OK, EINVAL, EHIP, ENOMEM = 0, -1, -2, -3
-PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE = range(5)
+PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE, PAIR_ABORTED = range(6)
 FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_MULTI_LAUNCH = 0x1, 0x2, 0x4, 0x8
 PGO_INIT_CHAIN = 0x1
 
@@ -62,6 +62,8 @@ _EXPORTS = {
     "s3a_autotune": (ctypes.c_int, [c_void_p, ctypes.POINTER(AlignDesc), ctypes.POINTER(Tuning), c_void_p]),
     "s3a_set_tuning": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.POINTER(Tuning)]),
     "s3a_get_tuning": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Tuning)]),
+    "s3a_set_timing": (ctypes.c_int, [c_void_p, ctypes.c_int]),
+    "s3a_kernel_time": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -242,6 +244,16 @@ class Handle:
             return
         t = Tuning(wg, items, occupancy, window)
         _check(self.lib.s3a_set_tuning(self.h, dtype, ctypes.byref(t)))
+
+    def set_timing(self, on):
+        _check(self.lib.s3a_set_timing(self.h, 1 if on else 0))
+
+    def kernel_time(self):
+        """(summed ms, launches) of the dominant kernel since the last query."""
+        ms = ctypes.c_double()
+        n = ctypes.c_int32()
+        _check(self.lib.s3a_kernel_time(self.h, ctypes.byref(ms), ctypes.byref(n)), self.h)
+        return ms.value, n.value
 
     def get_tuning(self, dtype, n_points):
         t = Tuning()

@@ -36,8 +36,8 @@ __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __rest
   for (int j = 0; j < 7; ++j) { pl[j] = cd->planes[j]; gout[j] = cd->grad[j]; }
   const float tau = sh.tau, delta = sh.delta_f;
   for (int t = (int)blockIdx.x; t < total; t += (int)gridDim.x) {
-    const TileDesc td = w.tiles[t];
-    const PointParams P = w.params[td.pair];
+    const TileDesc td = load_tile(w.tiles + t);
+    const PointParams P = load_params(w.params + td.pair);
     double acc[NSTAT];
 #pragma unroll
     for (int j = 0; j < NSTAT; ++j) acc[j] = 0.0;

@@ -71,6 +71,44 @@ __device__ inline bool finite7(const float* x) {
   return f;
 }
 
+// ---------------------------------------------------------------- uniform parameters
+
+// The per-pair parameters are the same for every lane of a tile: read them
+// once and keep them in scalar registers.
+__device__ inline float uniform_f32(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline int uniform_i32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline double uniform_f64(double v) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+__device__ inline PointParams load_params(const PointParams* p) {
+  PointParams r;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) { r.M[i] = uniform_f64(p->M[i]); r.Mf[i] = uniform_f32(p->Mf[i]); }
+#pragma unroll
+  for (int i = 0; i < 3; ++i) { r.t[i] = uniform_f64(p->t[i]); r.c[i] = uniform_f64(p->c[i]); }
+  r.inv_C = uniform_f32(p->inv_C);
+  r.scale = uniform_f32(p->scale);
+  r.L = uniform_f32(p->L);
+  r.active = uniform_i32(p->active);
+  r.pad = 0;
+  return r;
+}
+
+__device__ inline TileDesc load_tile(const TileDesc* p) {
+  TileDesc r;
+  const long long b = p->begin, e = p->end, l = p->lo;
+  r.begin = ((long long)(unsigned)uniform_i32((int)(b >> 32)) << 32) | (unsigned)uniform_i32((int)b);
+  r.end = ((long long)(unsigned)uniform_i32((int)(e >> 32)) << 32) | (unsigned)uniform_i32((int)e);
+  r.lo = ((long long)(unsigned)uniform_i32((int)(l >> 32)) << 32) | (unsigned)uniform_i32((int)l);
+  r.pair = uniform_i32(p->pair);
+  r.pad = 0;
+  return r;
+}
+
 // ---------------------------------------------------------------- per-point terms
 
 // Closed-form start: weighted raw moments, accumulated in FP64 (the products

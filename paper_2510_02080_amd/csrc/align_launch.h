@@ -30,5 +30,6 @@ hipError_t launch_finalize_adjoint(const Shape& sh, const CallDesc* cd, const Wo
 hipError_t launch_persistent(int dtype, const LaunchCfg& lc, const Shape& sh, const CallDesc* cd, const Work& w,
                              int grid, hipStream_t st);
 hipError_t launch_fill_zero(uint32_t* p, int64_t n, hipStream_t st);
+hipError_t launch_init_outputs(const Shape& sh, const CallDesc* cd, hipStream_t st);
 
 }  // namespace s3a

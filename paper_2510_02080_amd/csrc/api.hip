@@ -14,7 +14,7 @@ using namespace s3a;
 
 namespace {
 
-constexpr bool kPersistentAvailable = false;
+constexpr bool kPersistentAvailable = true;
 
 struct GraphKey {
   int dtype, n_pairs, K, wg, items, occupancy, window, persistent;
@@ -57,6 +57,8 @@ struct s3a_handle {
   std::vector<TuneEntry> tuned;
   PgoWorkspace* pgo = nullptr;
   CallDesc* desc = nullptr;
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
 };
 
 namespace {
@@ -71,6 +73,29 @@ int hip_fail(s3a_handle* h, hipError_t e) {
     hipError_t e_ = (expr);                   \
     if (e_ != hipSuccess) return hip_fail(h, e_); \
   } while (0)
+
+// Event pair around one launch of a call's dominant kernel (timing mode).
+struct TimedLaunch {
+  s3a_handle* h;
+  hipStream_t st;
+  std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+  TimedLaunch(s3a_handle* hh, hipStream_t s) : h(hh), st(s) {
+    if (!h || !h->timing) return;
+    if (!h->ev_free.empty()) {
+      ev = h->ev_free.back();
+      h->ev_free.pop_back();
+    } else {
+      (void)hipEventCreate(&ev.first);
+      (void)hipEventCreate(&ev.second);
+    }
+    (void)hipEventRecord(ev.first, st);
+  }
+  ~TimedLaunch() {
+    if (!ev.first) return;
+    (void)hipEventRecord(ev.second, st);
+    h->ev_used.push_back(ev);
+  }
+};
 
 struct DeviceGuard {
   int prev = -1;
@@ -228,7 +253,10 @@ hipError_t enqueue_batched_multi(s3a_handle* h, int dtype, const LaunchCfg& lc, 
   const int npass = 1 + sh.K + ((sh.flags & S3A_FLAG_FINAL_COST) ? 1 : 0);
   for (int pass = 0; pass < npass; ++pass) {
     const int mode = pass == 0 ? MODE_MOMENTS : MODE_GN;
-    e = launch_pass(dtype, mode, lc, sh, dcd, h->w, 0, -1, grid, st);
+    {
+      TimedLaunch tl(h, st);
+      e = launch_pass(dtype, mode, lc, sh, dcd, h->w, 0, -1, grid, st);
+    }
     if (e != hipSuccess) return e;
     const int kind = pass == 0 ? 0 : (pass <= sh.K ? 1 : 2);
     e = launch_finalize(kind, sh, dcd, h->w, pass, 0, sh.n_pairs, st);
@@ -246,7 +274,10 @@ hipError_t enqueue_batched(s3a_handle* h, int dtype, const LaunchCfg& lc, const 
   if (e != hipSuccess) return e;
   e = launch_fill_zero(h->w.flags, (int64_t)sh.n_pairs, st);
   if (e != hipSuccess) return e;
+  e = launch_init_outputs(sh, dcd, st);
+  if (e != hipSuccess) return e;
   const int grid = lc.occupancy * h->n_cu;
+  TimedLaunch tl(h, st);
   return launch_persistent(dtype, lc, sh, dcd, h->w, grid, st);
 }
 
@@ -301,6 +332,8 @@ int s3a_destroy(s3a_handle* h) {
   clear_graphs(h);
   if (h->ws) (void)hipFree(h->ws);
   pgo_free(h->pgo);
+  for (auto& ev : h->ev_used) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
+  for (auto& ev : h->ev_free) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
   delete h;
   return S3A_OK;
@@ -339,7 +372,10 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
       const PairSched& s = sched[k];
       for (int pass = 0; pass < npass; ++pass) {
         const int mode = pass == 0 ? MODE_MOMENTS : MODE_GN;
-        S3A_TRY(launch_pass(d->dtype, mode, lc, sh, dcd, h->w, s.tile0, s.tile0 + s.ntiles, s.ntiles, st));
+        {
+          TimedLaunch tl(h, st);
+          S3A_TRY(launch_pass(d->dtype, mode, lc, sh, dcd, h->w, s.tile0, s.tile0 + s.ntiles, s.ntiles, st));
+        }
         const int kind = pass == 0 ? 0 : (pass <= sh.K ? 1 : 2);
         S3A_TRY(launch_finalize(kind, sh, dcd, h->w, pass, k, 1, st));
       }
@@ -348,7 +384,7 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
   }
 
   const bool persistent = kPersistentAvailable && !(d->flags & S3A_FLAG_MULTI_LAUNCH);
-  if (d->flags & S3A_FLAG_NO_GRAPH) {
+  if ((d->flags & S3A_FLAG_NO_GRAPH) || h->timing) {
     S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
     S3A_TRY(enqueue_batched(h, d->dtype, lc, sh, dcd, persistent, st));
     return S3A_OK;
@@ -428,7 +464,10 @@ int s3a_align_cost(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* S, co
   S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
   S3A_TRY(launch_sched(sh, dcd, h->w, st));
   S3A_TRY(launch_prep(sh, dcd, h->w, 0, st));
-  S3A_TRY(launch_pass(d->dtype, MODE_COST, lc, sh, dcd, h->w, 0, -1, grid_for(h, lc, mt), st));
+  {
+    TimedLaunch tl(h, st);
+    S3A_TRY(launch_pass(d->dtype, MODE_COST, lc, sh, dcd, h->w, 0, -1, grid_for(h, lc, mt), st));
+  }
   S3A_TRY(launch_finalize_cost(sh, dcd, h->w, st));
   return S3A_OK;
 }
@@ -464,9 +503,37 @@ int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* d, const s3a_s
   S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
   S3A_TRY(launch_sched(sh, dcd, h->w, st));
   S3A_TRY(launch_prep(sh, dcd, h->w, 1, st));
-  S3A_TRY(launch_adjoint(d->dtype, lc, sh, dcd, h->w, grid_for(h, lc, mt), st));
+  {
+    TimedLaunch tl(h, st);
+    S3A_TRY(launch_adjoint(d->dtype, lc, sh, dcd, h->w, grid_for(h, lc, mt), st));
+  }
   S3A_TRY(launch_finalize_adjoint(sh, dcd, h->w, st));
   return S3A_OK;
+}
+
+int s3a_set_timing(s3a_handle* h, int on) {
+  if (!h) return S3A_EINVAL;
+  h->timing = on != 0;
+  return S3A_OK;
+}
+
+int s3a_kernel_time(s3a_handle* h, double* ms, int32_t* launches) {
+  if (!h || !ms || !launches) return S3A_EINVAL;
+  DeviceGuard g(h->device);
+  double total = 0.0;
+  int rc = S3A_OK;
+  for (auto& ev : h->ev_used) {
+    hipError_t e = hipEventSynchronize(ev.second);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev.first, ev.second);
+    if (e != hipSuccess) rc = hip_fail(h, e);
+    total += t;
+  }
+  *launches = (int32_t)h->ev_used.size();
+  *ms = total;
+  h->ev_free.insert(h->ev_free.end(), h->ev_used.begin(), h->ev_used.end());
+  h->ev_used.clear();
+  return rc;
 }
 
 int s3a_set_tuning(s3a_handle* h, int32_t dtype, const s3a_tuning* t) {

@@ -221,6 +221,40 @@ S3A_HD bool cholesky_solve(double* H, const double* b, double* x) {
   return true;
 }
 
+// Cholesky solve of the SPD system H x = b with H given as its packed lower
+// triangle (row i holds H[i][0..i], at offset i (i + 1) / 2), overwritten by
+// the factor. Returns false when a pivot is not positive.
+template <int N>
+S3A_HD bool cholesky_solve_packed(double* L, const double* b, double* x) {
+  for (int j = 0; j < N; ++j) {
+    const int rj = j * (j + 1) / 2;
+    double d = L[rj + j];
+    for (int k = 0; k < j; ++k) d -= L[rj + k] * L[rj + k];
+    if (!(d > 0.0)) return false;
+    d = sqrt(d);
+    L[rj + j] = d;
+    for (int i = j + 1; i < N; ++i) {
+      const int ri = i * (i + 1) / 2;
+      double v = L[ri + j];
+      for (int k = 0; k < j; ++k) v -= L[ri + k] * L[rj + k];
+      L[ri + j] = v / d;
+    }
+  }
+  double y[N];
+  for (int i = 0; i < N; ++i) {
+    const int ri = i * (i + 1) / 2;
+    double v = b[i];
+    for (int k = 0; k < i; ++k) v -= L[ri + k] * y[k];
+    y[i] = v / L[ri + i];
+  }
+  for (int i = N - 1; i >= 0; --i) {
+    double v = y[i];
+    for (int k = i + 1; k < N; ++k) v -= L[k * (k + 1) / 2 + i] * x[k];
+    x[i] = v / L[i * (i + 1) / 2 + i];
+  }
+  return true;
+}
+
 // F_n(sigma) = int_0^1 exp(sigma u) u^n du.
 S3A_HD double int_exp_pow(int n, double sg) {
   if (fabs(sg) < 2.0) {  // power series sum_k sg^k / (k! (n + k + 1))

@@ -1,10 +1,675 @@
+// Sim(3) pose-graph optimisation (Sec. III-E) on the GPU in FP64.
+//
+// Nodes are submap poses T_t; edge (i, j) carries T_ij and the residual
+// e_ij = Log(T_ij^{-1} T_i^{-1} T_j). Each iteration is one Gauss-Newton step
+// on sum_ij rho_pg(sqrt(e^T Omega e)) (Huber weights recomputed per
+// iteration; plain chi^2 when delta_pg = inf), with left perturbations
+// T <- Exp(xi) T and the gauge node held fixed:
+//   de/dxi_j = J_r(e)^{-1} Ad(T_j^{-1}) =: A,   de/dxi_i = -A,
+// so edge (i, j) adds M = psi A^T Omega A to the diagonal blocks of i and j,
+// -M to the off-diagonal block (i, j), and -/+ psi A^T Omega e to g_i / g_j.
+//
+// Host (once per graph topology): minimum-degree ordering of the free nodes,
+// symbolic block Cholesky (column structures, elimination tree, levels), and
+// fixed-order lists: which edges assemble into which block, and which pairs of
+// factor blocks update which target block.
+// Device, per iteration: one kernel linearises every edge (one lane per edge);
+// one workgroup then assembles H and g, factorises level by level (blocks of a
+// level are independent), solves L L^T dx = -g level by level, and applies
+// T <- Exp(dx) T. All waits are workgroup barriers.
+#include <string.h>
+
+#include <algorithm>
+#include <deque>
+#include <set>
+#include <vector>
+
+#include "align_launch.h"
+#include "finalize.h"
 #include "pgo.h"
 
 namespace s3a {
-struct PgoWorkspace {};
-int pgo_solve(PgoWorkspace**, int*, int32_t, int32_t, const int32_t*, const s3a_sim3*, const double*, s3a_sim3*,
-              const s3a_pgo_params*, s3a_pgo_report*, hipStream_t) {
-  return S3A_EINVAL;
+
+// ------------------------------------------------------------------ device data
+
+struct PgoDev {
+  int32_t n_nodes, n_edges, m, gauge;   // m = free nodes
+  int32_t nblk;                         // off-diagonal factor blocks
+  int32_t nlev;
+  const int32_t* ei;                    // [E] node i
+  const int32_t* ej;                    // [E] node j
+  const int32_t* pos;                   // [n] node -> elimination position (-1: gauge)
+  const int32_t* node;                  // [m] position -> node
+  // off-diagonal blocks of L, column-major: column c owns blocks [col_ptr[c], col_ptr[c+1])
+  const int32_t* col_ptr;               // [m+1]
+  const int32_t* blk_row;               // [nblk] row position
+  const int32_t* blk_col;               // [nblk] column position
+  // assembly: diagonal of position c gets +M of edges dg_edge[dg_ptr[c]..]; block b gets -M of
+  // edges ob_edge[ob_ptr[b]..]; g of position c gets sign * v of edges (gv_edge, gv_sign)
+  const int32_t* dg_ptr; const int32_t* dg_edge;
+  const int32_t* ob_ptr; const int32_t* ob_edge;
+  const int32_t* gv_ptr; const int32_t* gv_edge; const int8_t* gv_sign;
+  // updates: target t (0..m-1 diagonal of position t, m + b off-diagonal block b) gets
+  // -= L_a L_b^T for (a, b) in up_a/up_b[up_ptr[t]..]; a, b index blocks (always off-diagonal)
+  const int32_t* up_ptr; const int32_t* up_a; const int32_t* up_b;
+  // level schedule (from the leaves)
+  const int32_t* lev_ptr; const int32_t* lev_col;
+  // rows of L for the forward solve: blocks (c, k), k < c
+  const int32_t* row_ptr; const int32_t* row_blk;
+  // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
+  const int32_t* chain; int32_t n_chain;
+  // numeric storage
+  double* Ld;     // [m][49] diagonal blocks (lower Cholesky factor after factorisation)
+  double* Lb;     // [nblk][49]
+  double* g;      // [m][7]  gradient, then solution
+  double* M;      // [E][49] per-edge psi A^T Omega A
+  double* v;      // [E][7]  per-edge psi A^T Omega e
+  double* r2;     // [E]     e^T Omega e
+  double* chi2;   // [iters + 1]
+  int32_t* status;
+};
+
+__device__ inline Sim3d ld_pose(const s3a_sim3* p) { return load_sim3(p); }
+
+// Breadth-first chaining from the gauge node: T_j = T_i T_ij (dir 0) or
+// T_i = T_j T_ij^{-1} (dir 1). One lane; the order is a tree traversal.
+__global__ void k_pgo_chain(PgoDev d, const s3a_sim3* __restrict__ Tm, s3a_sim3* T) {
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  for (int k = 0; k < d.n_nodes; ++k) store_sim3(T + k, sim3_identity());
+  for (int c = 0; c < d.n_chain; ++c) {
+    const int nd = d.chain[4 * c], par = d.chain[4 * c + 1], e = d.chain[4 * c + 2], dir = d.chain[4 * c + 3];
+    const Sim3d Tp = ld_pose(T + par);
+    const Sim3d Te = ld_pose(Tm + e);
+    store_sim3(T + nd, dir == 0 ? sim3_compose(Tp, Te) : sim3_compose(Tp, sim3_inverse(Te)));
+  }
 }
-void pgo_free(PgoWorkspace* ws) { delete ws; }
+
+// One lane per edge: residual, Jacobian A, Huber weight, M = psi A^T Om A, v = psi A^T Om e.
+__global__ __launch_bounds__(128) void k_pgo_linearize(PgoDev d, const s3a_sim3* __restrict__ Tm,
+                                                      const double* __restrict__ omega, const s3a_sim3* __restrict__ T,
+                                                      double huber, int r2_only) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= d.n_edges) return;
+  const Sim3d Ti = ld_pose(T + d.ei[k]);
+  const Sim3d Tj = ld_pose(T + d.ej[k]);
+  const Sim3d Tij = ld_pose(Tm + k);
+  const Sim3d Z = sim3_compose(sim3_compose(sim3_inverse(Tij), sim3_inverse(Ti)), Tj);
+  double e[7];
+  sim3_log(Z, e);
+  const double* Om = omega ? omega + 49 * k : nullptr;
+  double Oe[7];
+  for (int a = 0; a < 7; ++a) {
+    double s = 0.0;
+    if (Om) for (int b = 0; b < 7; ++b) s += Om[7 * a + b] * e[b];
+    else s = e[a];
+    Oe[a] = s;
+  }
+  double q = 0.0;
+  for (int a = 0; a < 7; ++a) q += e[a] * Oe[a];
+  d.r2[k] = q;
+  if (r2_only) return;
+  const double r = sqrt(q > 0.0 ? q : 0.0);
+  const double psi = r <= huber ? 1.0 : huber / r;
+  double Jr[49], Jri[49], Ad[49];
+  sim3_jacobian(e, -1.0, Jr);
+  if (!inv7(Jr, Jri)) {
+    for (int a = 0; a < 49; ++a) d.M[49 * k + a] = __builtin_nan("");
+    for (int a = 0; a < 7; ++a) d.v[7 * k + a] = __builtin_nan("");
+    return;
+  }
+  sim3_Ad(sim3_inverse(Tj), Ad);
+  double A[49];
+  for (int a = 0; a < 7; ++a)
+    for (int b = 0; b < 7; ++b) {
+      double s = 0.0;
+      for (int c = 0; c < 7; ++c) s += Jri[7 * a + c] * Ad[7 * c + b];
+      A[7 * a + b] = s;
+    }
+  // Om A (7x7), then M = psi A^T (Om A), v = psi A^T Om e
+  double OA[49];
+  for (int a = 0; a < 7; ++a)
+    for (int b = 0; b < 7; ++b) {
+      double s = 0.0;
+      if (Om) for (int c = 0; c < 7; ++c) s += Om[7 * a + c] * A[7 * c + b];
+      else s = A[7 * a + b];
+      OA[7 * a + b] = s;
+    }
+  for (int a = 0; a < 7; ++a) {
+    for (int b = 0; b < 7; ++b) {
+      double s = 0.0;
+      for (int c = 0; c < 7; ++c) s += A[7 * c + a] * OA[7 * c + b];
+      d.M[49 * k + 7 * a + b] = psi * s;
+    }
+    double s = 0.0;
+    for (int c = 0; c < 7; ++c) s += A[7 * c + a] * Oe[c];
+    d.v[7 * k + a] = psi * s;
+  }
+}
+
+constexpr int PGO_WG = 1024;
+
+// Deterministic workgroup sum of per-lane doubles (fixed tree).
+__device__ inline double wg_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) sh[wv] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    for (int q = 0; q < PGO_WG / 64; ++q) s += sh[q];
+    sh[PGO_WG / 64] = s;
+  }
+  __syncthreads();
+  s = sh[PGO_WG / 64];
+  __syncthreads();
+  return s;
+}
+
+// One Gauss-Newton iteration on one workgroup: chi^2, assembly, factorisation,
+// solves, update. `it` indexes the chi^2 record.
+__global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, double lambda, int it, int update) {
+  __shared__ double sh[PGO_WG / 64 + 1];
+  __shared__ int s_fail;
+  const int tid = threadIdx.x;
+  if (*d.status != 0) return;
+  // chi^2 at the linearisation point (fixed order)
+  double part = 0.0;
+  for (int k = tid; k < d.n_edges; k += PGO_WG) part += d.r2[k];
+  const double c2 = wg_sum(part, sh);
+  if (tid == 0) d.chi2[it] = c2;
+  if (!update) return;
+  if (tid == 0) s_fail = 0;
+  // ---- assembly (diagonal blocks, off-diagonal blocks, gradient)
+  for (int x = tid; x < d.m * 49; x += PGO_WG) {
+    const int c = x / 49, a = x % 49;
+    double s = 0.0;
+    for (int q = d.dg_ptr[c]; q < d.dg_ptr[c + 1]; ++q) s += d.M[49 * d.dg_edge[q] + a];
+    if (lambda > 0.0 && a % 8 == 0) s += lambda * s;
+    d.Ld[x] = s;
+  }
+  for (int x = tid; x < d.nblk * 49; x += PGO_WG) {
+    const int b = x / 49, a = x % 49;
+    double s = 0.0;
+    for (int q = d.ob_ptr[b]; q < d.ob_ptr[b + 1]; ++q) s -= d.M[49 * d.ob_edge[q] + a];
+    d.Lb[x] = s;
+  }
+  for (int x = tid; x < d.m * 7; x += PGO_WG) {
+    const int c = x / 7, a = x % 7;
+    double s = 0.0;
+    for (int q = d.gv_ptr[c]; q < d.gv_ptr[c + 1]; ++q) s += (double)d.gv_sign[q] * d.v[7 * d.gv_edge[q] + a];
+    d.g[x] = -s;  // right-hand side -g
+  }
+  __syncthreads();
+  // ---- factorisation, level by level
+  for (int l = 0; l < d.nlev; ++l) {
+    const int c0 = d.lev_ptr[l], c1 = d.lev_ptr[l + 1];
+    // (A) targets of this level's columns: diagonal blocks and off-diagonal blocks,
+    // one lane per element: S -= sum_k L_a L_b^T
+    for (int cc = c0; cc < c1; ++cc) {
+      const int c = d.lev_col[cc];
+      const int nb = d.col_ptr[c + 1] - d.col_ptr[c];
+      for (int x = tid; x < (nb + 1) * 49; x += PGO_WG) {
+        const int tb = x / 49, a = x % 49, r = a / 7, s = a % 7;
+        const int target = tb == 0 ? c : d.m + d.col_ptr[c] + tb - 1;
+        double acc = 0.0;
+        for (int q = d.up_ptr[target]; q < d.up_ptr[target + 1]; ++q) {
+          const double* La = d.Lb + 49 * d.up_a[q];
+          const double* Lc = d.Lb + 49 * d.up_b[q];
+          for (int u = 0; u < 7; ++u) acc += La[7 * r + u] * Lc[7 * s + u];
+        }
+        double* dst = tb == 0 ? d.Ld + 49 * c + a : d.Lb + 49 * (d.col_ptr[c] + tb - 1) + a;
+        *dst -= acc;
+      }
+    }
+    __syncthreads();
+    // (B) dense Cholesky of each diagonal block of the level (one lane per column)
+    for (int cc = c0 + tid; cc < c1; cc += PGO_WG) {
+      double* D = d.Ld + 49 * d.lev_col[cc];
+      bool ok = true;
+      for (int j = 0; j < 7 && ok; ++j) {
+        double s = D[8 * j];
+        for (int k = 0; k < j; ++k) s -= D[7 * j + k] * D[7 * j + k];
+        if (!(s > 0.0)) { ok = false; break; }
+        s = sqrt(s);
+        D[8 * j] = s;
+        for (int i = j + 1; i < 7; ++i) {
+          double v = D[7 * i + j];
+          for (int k = 0; k < j; ++k) v -= D[7 * i + k] * D[7 * j + k];
+          D[7 * i + j] = v / s;
+        }
+      }
+      for (int i = 0; i < 7; ++i)
+        for (int j = i + 1; j < 7; ++j) D[7 * i + j] = 0.0;
+      if (!ok) s_fail = 1;
+    }
+    __syncthreads();
+    if (s_fail) break;
+    // (C) L_ij = S_ij L_jj^{-T}: one lane per block row
+    for (int cc = c0; cc < c1; ++cc) {
+      const int c = d.lev_col[cc];
+      const double* D = d.Ld + 49 * c;
+      const int b0 = d.col_ptr[c], nb = d.col_ptr[c + 1] - b0;
+      for (int x = tid; x < nb * 7; x += PGO_WG) {
+        double* row = d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7);
+        double y[7];
+        for (int j = 0; j < 7; ++j) {
+          double v = row[j];
+          for (int k = 0; k < j; ++k) v -= y[k] * D[7 * j + k];
+          y[j] = v / D[8 * j];
+        }
+        for (int j = 0; j < 7; ++j) row[j] = y[j];
+      }
+    }
+    __syncthreads();
+  }
+  if (s_fail) {
+    if (tid == 0) *d.status = 2;
+    return;
+  }
+  // ---- forward solve L y = -g, levels from the leaves; one wavefront per column
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int l = 0; l < d.nlev; ++l) {
+    for (int cc = d.lev_ptr[l] + wv; cc < d.lev_ptr[l + 1]; cc += PGO_WG / 64) {
+      const int c = d.lev_col[cc];
+      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (int q = d.row_ptr[c] + lane; q < d.row_ptr[c + 1]; q += 64) {
+        const int b = d.row_blk[q];
+        const double* L = d.Lb + 49 * b;
+        const double* y = d.g + 7 * d.blk_col[b];
+        for (int r = 0; r < 7; ++r)
+          for (int u = 0; u < 7; ++u) acc[r] += L[7 * r + u] * y[u];
+      }
+      for (int r = 0; r < 7; ++r) acc[r] = wave_sum(acc[r]);
+      if (lane == 0) {
+        const double* D = d.Ld + 49 * c;
+        double* y = d.g + 7 * c;
+        double t[7];
+        for (int r = 0; r < 7; ++r) {
+          double v = y[r] - acc[r];
+          for (int k = 0; k < r; ++k) v -= D[7 * r + k] * t[k];
+          t[r] = v / D[8 * r];
+        }
+        for (int r = 0; r < 7; ++r) y[r] = t[r];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- backward solve L^T x = y, levels from the root
+  for (int l = d.nlev - 1; l >= 0; --l) {
+    for (int cc = d.lev_ptr[l] + wv; cc < d.lev_ptr[l + 1]; cc += PGO_WG / 64) {
+      const int c = d.lev_col[cc];
+      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+      for (int b = d.col_ptr[c] + lane; b < d.col_ptr[c + 1]; b += 64) {
+        const double* L = d.Lb + 49 * b;
+        const double* x = d.g + 7 * d.blk_row[b];
+        for (int r = 0; r < 7; ++r)
+          for (int u = 0; u < 7; ++u) acc[u] += L[7 * r + u] * x[r];
+      }
+      for (int r = 0; r < 7; ++r) acc[r] = wave_sum(acc[r]);
+      if (lane == 0) {
+        const double* D = d.Ld + 49 * c;
+        double* x = d.g + 7 * c;
+        double t[7];
+        for (int r = 6; r >= 0; --r) {
+          double v = x[r] - acc[r];
+          for (int k = r + 1; k < 7; ++k) v -= D[7 * k + r] * t[k];
+          t[r] = v / D[8 * r];
+        }
+        for (int r = 0; r < 7; ++r) x[r] = t[r];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- update T <- Exp(dx) T for the free nodes
+  for (int c = tid; c < d.m; c += PGO_WG) {
+    const int nd = d.node[c];
+    const Sim3d E = sim3_exp(d.g + 7 * c);
+    store_sim3(T + nd, sim3_compose(E, ld_pose(T + nd)));
+  }
+}
+
+// ------------------------------------------------------------------ host
+
+struct PgoWorkspace {
+  int32_t n_nodes = -1, n_edges = -1, gauge = -1;
+  std::vector<int32_t> ij;  // topology the symbolic analysis was made for
+  void* buf = nullptr;
+  PgoDev dev{};
+  int32_t cap_iters = 0;
+  int64_t nnz_blocks = 0;
+};
+
+namespace {
+
+struct Symbolic {
+  int m = 0, nblk = 0, nlev = 0;
+  std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
+      up_ptr, up_a, up_b, lev_ptr, lev_col, row_ptr, row_blk, chain;
+  std::vector<int8_t> gv_sign;
+};
+
+// Minimum degree (smallest current degree, ties by node id) on the free nodes,
+// by explicit elimination of the node graph.
+std::vector<int32_t> min_degree(int n, int gauge, const std::vector<std::set<int>>& adj0) {
+  std::vector<std::set<int>> adj(adj0);
+  std::set<std::pair<int, int>> pq;
+  std::vector<char> done(n, 0);
+  for (int v = 0; v < n; ++v)
+    if (v != gauge) pq.insert({(int)adj[v].size(), v});
+  std::vector<int32_t> order;
+  while (!pq.empty()) {
+    const int v = pq.begin()->second;
+    pq.erase(pq.begin());
+    done[v] = 1;
+    order.push_back(v);
+    std::vector<int> nb(adj[v].begin(), adj[v].end());
+    for (int a : nb) {
+      pq.erase({(int)adj[a].size(), a});
+      adj[a].erase(v);
+      for (int b : nb)
+        if (b != a) adj[a].insert(b);
+      pq.insert({(int)adj[a].size(), a});
+    }
+    adj[v].clear();
+  }
+  return order;
+}
+
+Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
+  Symbolic S;
+  std::vector<std::set<int>> adj(n);
+  for (int k = 0; k < E; ++k) {
+    const int i = ij[2 * k], j = ij[2 * k + 1];
+    if (i != gauge && j != gauge) {
+      adj[i].insert(j);
+      adj[j].insert(i);
+    }
+  }
+  const std::vector<int32_t> order = min_degree(n, gauge, adj);
+  const int m = (int)order.size();
+  S.m = m;
+  S.pos.assign(n, -1);
+  S.node = order;
+  for (int c = 0; c < m; ++c) S.pos[order[c]] = c;
+  // symbolic factorisation: struct(c) = rows > c, merged into the parent
+  std::vector<std::set<int>> cs(m);
+  for (int k = 0; k < E; ++k) {
+    const int a = S.pos[ij[2 * k]], b = S.pos[ij[2 * k + 1]];
+    if (a < 0 || b < 0) continue;
+    cs[std::min(a, b)].insert(std::max(a, b));
+  }
+  std::vector<int> parent(m, -1);
+  for (int c = 0; c < m; ++c) {
+    if (cs[c].empty()) continue;
+    const int p = *cs[c].begin();
+    parent[c] = p;
+    for (int r : cs[c])
+      if (r != p) cs[p].insert(r);
+  }
+  S.col_ptr.assign(m + 1, 0);
+  for (int c = 0; c < m; ++c) S.col_ptr[c + 1] = S.col_ptr[c] + (int)cs[c].size();
+  S.nblk = S.col_ptr[m];
+  S.blk_row.resize(S.nblk);
+  S.blk_col.resize(S.nblk);
+  std::vector<std::vector<std::pair<int, int>>> colrows(m);  // (row, block)
+  for (int c = 0; c < m; ++c) {
+    int b = S.col_ptr[c];
+    for (int r : cs[c]) {
+      S.blk_row[b] = r;
+      S.blk_col[b] = c;
+      colrows[c].push_back({r, b});
+      ++b;
+    }
+  }
+  auto block_of = [&](int r, int c) -> int {  // r > c
+    auto& v = colrows[c];
+    auto it = std::lower_bound(v.begin(), v.end(), std::make_pair(r, -1));
+    return (it != v.end() && it->first == r) ? it->second : -1;
+  };
+  // assembly lists
+  std::vector<std::vector<int>> dg(m), ob(S.nblk), gv(m);
+  std::vector<std::vector<int8_t>> gs(m);
+  for (int k = 0; k < E; ++k) {
+    const int a = S.pos[ij[2 * k]], b = S.pos[ij[2 * k + 1]];
+    if (a >= 0) { dg[a].push_back(k); gv[a].push_back(k); gs[a].push_back(-1); }
+    if (b >= 0) { dg[b].push_back(k); gv[b].push_back(k); gs[b].push_back(+1); }
+    if (a >= 0 && b >= 0) ob[block_of(std::max(a, b), std::min(a, b))].push_back(k);
+  }
+  auto flatten = [](const std::vector<std::vector<int>>& L, std::vector<int32_t>& ptr, std::vector<int32_t>& val) {
+    ptr.assign(L.size() + 1, 0);
+    for (size_t i = 0; i < L.size(); ++i) ptr[i + 1] = ptr[i] + (int)L[i].size();
+    val.clear();
+    for (auto& v : L) val.insert(val.end(), v.begin(), v.end());
+  };
+  flatten(dg, S.dg_ptr, S.dg_edge);
+  flatten(ob, S.ob_ptr, S.ob_edge);
+  flatten(gv, S.gv_ptr, S.gv_edge);
+  for (auto& v : gs) S.gv_sign.insert(S.gv_sign.end(), v.begin(), v.end());
+  // update lists: column k contributes L(a,k) L(b,k)^T to target (a, b), a >= b
+  std::vector<std::vector<std::pair<int, int>>> up(m + S.nblk);
+  for (int k = 0; k < m; ++k) {
+    const auto& rows = colrows[k];
+    for (size_t x = 0; x < rows.size(); ++x)
+      for (size_t y = 0; y <= x; ++y) {
+        const int ra = rows[x].first, rb = rows[y].first;  // ra >= rb
+        const int t = (ra == rb) ? ra : S.m + block_of(ra, rb);
+        up[t].push_back({rows[x].second, rows[y].second});
+      }
+  }
+  S.up_ptr.assign(m + S.nblk + 1, 0);
+  for (size_t t = 0; t < up.size(); ++t) S.up_ptr[t + 1] = S.up_ptr[t] + (int)up[t].size();
+  for (auto& v : up)
+    for (auto& p : v) { S.up_a.push_back(p.first); S.up_b.push_back(p.second); }
+  // levels from the leaves
+  std::vector<int> lev(m, 0);
+  int nlev = 0;
+  for (int c = 0; c < m; ++c) {
+    if (parent[c] >= 0) lev[parent[c]] = std::max(lev[parent[c]], lev[c] + 1);
+    nlev = std::max(nlev, lev[c] + 1);
+  }
+  S.nlev = nlev;
+  S.lev_ptr.assign(nlev + 1, 0);
+  for (int c = 0; c < m; ++c) S.lev_ptr[lev[c] + 1]++;
+  for (int l = 0; l < nlev; ++l) S.lev_ptr[l + 1] += S.lev_ptr[l];
+  S.lev_col.resize(m);
+  std::vector<int> fill(S.lev_ptr.begin(), S.lev_ptr.end() - 1);
+  for (int c = 0; c < m; ++c) S.lev_col[fill[lev[c]]++] = c;
+  // rows of L (blocks (c, k), k < c) for the forward solve
+  std::vector<std::vector<int>> rows(m);
+  for (int b = 0; b < S.nblk; ++b) rows[S.blk_row[b]].push_back(b);
+  flatten(rows, S.row_ptr, S.row_blk);
+  // chaining order (breadth-first from the gauge over edges in input order)
+  std::vector<std::vector<int>> inc(n);
+  for (int k = 0; k < E; ++k) {
+    inc[ij[2 * k]].push_back(k);
+    inc[ij[2 * k + 1]].push_back(k);
+  }
+  std::vector<char> placed(n, 0);
+  placed[gauge] = 1;
+  std::deque<int> q{gauge};
+  while (!q.empty()) {
+    const int a = q.front();
+    q.pop_front();
+    for (int k : inc[a]) {
+      const int i = ij[2 * k], j = ij[2 * k + 1];
+      if (i == a && !placed[j]) {
+        placed[j] = 1;
+        S.chain.insert(S.chain.end(), {j, i, k, 0});
+        q.push_back(j);
+      } else if (j == a && !placed[i]) {
+        placed[i] = 1;
+        S.chain.insert(S.chain.end(), {i, j, k, 1});
+        q.push_back(i);
+      }
+    }
+  }
+  return S;
+}
+
+template <typename T>
+T* carve(char*& p, size_t n) {
+  T* r = reinterpret_cast<T*>(p);
+  p += ((n * sizeof(T)) + 255) & ~size_t(255);
+  return r;
+}
+
+template <typename T>
+size_t bytes_of(size_t n) {
+  return ((n * sizeof(T)) + 255) & ~size_t(255);
+}
+
+int fail(int* last_hip, hipError_t e) {
+  if (last_hip) *last_hip = (int)e;
+  return e == hipErrorOutOfMemory ? S3A_ENOMEM : S3A_EHIP;
+}
+
+}  // namespace
+
+void pgo_free(PgoWorkspace* ws) {
+  if (!ws) return;
+  if (ws->buf) (void)hipFree(ws->buf);
+  delete ws;
+}
+
+int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edges, const int32_t* ij,
+              const s3a_sim3* T_meas, const double* omega, s3a_sim3* T, const s3a_pgo_params* params,
+              s3a_pgo_report* report, hipStream_t st) {
+  s3a_pgo_params p;
+  if (params) {
+    p = *params;
+  } else {
+    memset(&p, 0, sizeof(p));
+    p.iters = 20;
+    p.huber_delta = __builtin_inf();
+  }
+  if (n_nodes < 1 || n_edges < 0 || !T || (n_edges > 0 && (!ij || !T_meas))) return S3A_EINVAL;
+  if (p.iters < 0 || p.iters > 1000 || p.gauge < 0 || p.gauge >= n_nodes) return S3A_EINVAL;
+  if (!(p.huber_delta > 0.0) || !(p.lambda >= 0.0) || (p.flags & ~S3A_PGO_INIT_CHAIN) || p.reserved != 0)
+    return S3A_EINVAL;
+  for (int k = 0; k < n_edges; ++k) {
+    const int i = ij[2 * k], j = ij[2 * k + 1];
+    if (i < 0 || j < 0 || i >= n_nodes || j >= n_nodes || i == j) return S3A_EINVAL;
+  }
+  if (!*wsp) *wsp = new PgoWorkspace();
+  PgoWorkspace* ws = *wsp;
+  const bool same = ws->buf && ws->n_nodes == n_nodes && ws->n_edges == n_edges && ws->gauge == p.gauge &&
+                    ws->cap_iters >= p.iters + 1 && ws->ij.size() == 2 * (size_t)n_edges &&
+                    std::equal(ws->ij.begin(), ws->ij.end(), ij);
+  if (!same) {
+    const Symbolic S = analyse(n_nodes, n_edges, ij, p.gauge);
+    const int E = n_edges, m = S.m, nb = S.nblk;
+    const int iters_cap = std::max(p.iters + 1, 64);
+    size_t total = 0;
+    total += bytes_of<int32_t>(E) * 2 + bytes_of<int32_t>(n_nodes) + bytes_of<int32_t>(m);
+    total += bytes_of<int32_t>(m + 1) + bytes_of<int32_t>(nb) * 2;
+    total += bytes_of<int32_t>(S.dg_ptr.size()) + bytes_of<int32_t>(S.dg_edge.size());
+    total += bytes_of<int32_t>(S.ob_ptr.size()) + bytes_of<int32_t>(S.ob_edge.size());
+    total += bytes_of<int32_t>(S.gv_ptr.size()) + bytes_of<int32_t>(S.gv_edge.size()) + bytes_of<int8_t>(S.gv_sign.size());
+    total += bytes_of<int32_t>(S.up_ptr.size()) + bytes_of<int32_t>(S.up_a.size()) * 2;
+    total += bytes_of<int32_t>(S.lev_ptr.size()) + bytes_of<int32_t>(S.lev_col.size());
+    total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
+    total += bytes_of<int32_t>(S.chain.size() + 4);
+    total += bytes_of<double>(49 * (size_t)m) + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
+    total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
+    total += bytes_of<double>(iters_cap) + bytes_of<int32_t>(4);
+    if (ws->buf) {
+      (void)hipStreamSynchronize(st);
+      (void)hipFree(ws->buf);
+      ws->buf = nullptr;
+    }
+    void* buf = nullptr;
+    hipError_t e = hipMalloc(&buf, total);
+    if (e != hipSuccess) return fail(last_hip, e);
+    ws->buf = buf;
+    char* c = static_cast<char*>(buf);
+    PgoDev& d = ws->dev;
+    d.n_nodes = n_nodes; d.n_edges = E; d.m = m; d.gauge = p.gauge; d.nblk = nb; d.nlev = S.nlev;
+    std::vector<int32_t> ei(E), ej(E);
+    for (int k = 0; k < E; ++k) { ei[k] = ij[2 * k]; ej[k] = ij[2 * k + 1]; }
+    std::vector<std::pair<void*, std::pair<const void*, size_t>>> up;
+    auto put = [&](auto* dst, const auto& src) {
+      if (!src.empty()) up.push_back({(void*)dst, {(const void*)src.data(), src.size() * sizeof(src[0])}});
+    };
+    int32_t* p_ei = carve<int32_t>(c, E); put(p_ei, ei); d.ei = p_ei;
+    int32_t* p_ej = carve<int32_t>(c, E); put(p_ej, ej); d.ej = p_ej;
+    int32_t* p_pos = carve<int32_t>(c, n_nodes); put(p_pos, S.pos); d.pos = p_pos;
+    int32_t* p_node = carve<int32_t>(c, m); put(p_node, S.node); d.node = p_node;
+    int32_t* p_cp = carve<int32_t>(c, m + 1); put(p_cp, S.col_ptr); d.col_ptr = p_cp;
+    int32_t* p_br = carve<int32_t>(c, nb); put(p_br, S.blk_row); d.blk_row = p_br;
+    int32_t* p_bc = carve<int32_t>(c, nb); put(p_bc, S.blk_col); d.blk_col = p_bc;
+    int32_t* p_dgp = carve<int32_t>(c, S.dg_ptr.size()); put(p_dgp, S.dg_ptr); d.dg_ptr = p_dgp;
+    int32_t* p_dge = carve<int32_t>(c, S.dg_edge.size()); put(p_dge, S.dg_edge); d.dg_edge = p_dge;
+    int32_t* p_obp = carve<int32_t>(c, S.ob_ptr.size()); put(p_obp, S.ob_ptr); d.ob_ptr = p_obp;
+    int32_t* p_obe = carve<int32_t>(c, S.ob_edge.size()); put(p_obe, S.ob_edge); d.ob_edge = p_obe;
+    int32_t* p_gvp = carve<int32_t>(c, S.gv_ptr.size()); put(p_gvp, S.gv_ptr); d.gv_ptr = p_gvp;
+    int32_t* p_gve = carve<int32_t>(c, S.gv_edge.size()); put(p_gve, S.gv_edge); d.gv_edge = p_gve;
+    int8_t* p_gvs = carve<int8_t>(c, S.gv_sign.size()); put(p_gvs, S.gv_sign); d.gv_sign = p_gvs;
+    int32_t* p_upp = carve<int32_t>(c, S.up_ptr.size()); put(p_upp, S.up_ptr); d.up_ptr = p_upp;
+    int32_t* p_upa = carve<int32_t>(c, S.up_a.size()); put(p_upa, S.up_a); d.up_a = p_upa;
+    int32_t* p_upb = carve<int32_t>(c, S.up_b.size()); put(p_upb, S.up_b); d.up_b = p_upb;
+    int32_t* p_lvp = carve<int32_t>(c, S.lev_ptr.size()); put(p_lvp, S.lev_ptr); d.lev_ptr = p_lvp;
+    int32_t* p_lvc = carve<int32_t>(c, S.lev_col.size()); put(p_lvc, S.lev_col); d.lev_col = p_lvc;
+    int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
+    int32_t* p_rwb = carve<int32_t>(c, S.row_blk.size()); put(p_rwb, S.row_blk); d.row_blk = p_rwb;
+    int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
+    d.n_chain = (int32_t)(S.chain.size() / 4);
+    d.Ld = carve<double>(c, 49 * (size_t)m);
+    d.Lb = carve<double>(c, 49 * (size_t)nb + 49);
+    d.g = carve<double>(c, 7 * (size_t)m + 7);
+    d.M = carve<double>(c, 49 * (size_t)E + 49);
+    d.v = carve<double>(c, 7 * (size_t)E + 7);
+    d.r2 = carve<double>(c, E + 1);
+    d.chi2 = carve<double>(c, iters_cap);
+    d.status = carve<int32_t>(c, 4);
+    for (auto& u : up) {
+      e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
+      if (e != hipSuccess) return fail(last_hip, e);
+    }
+    e = hipStreamSynchronize(st);  // the host vectors go out of scope
+    if (e != hipSuccess) return fail(last_hip, e);
+    ws->n_nodes = n_nodes;
+    ws->n_edges = n_edges;
+    ws->gauge = p.gauge;
+    ws->ij.assign(ij, ij + 2 * (size_t)n_edges);
+    ws->cap_iters = iters_cap;
+    ws->nnz_blocks = (int64_t)nb + m;
+  }
+  PgoDev d = ws->dev;
+  hipError_t e = launch_fill_zero(reinterpret_cast<uint32_t*>(d.status), 1, st);
+  if (e != hipSuccess) return fail(last_hip, e);
+  if (p.flags & S3A_PGO_INIT_CHAIN) {
+    hipLaunchKernelGGL(k_pgo_chain, dim3(1), dim3(64), 0, st, d, T_meas, T);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+  }
+  const int lg = (n_edges + 127) / 128;
+  for (int it = 0; it <= p.iters; ++it) {
+    const int update = it < p.iters;
+    if (n_edges > 0) {
+      hipLaunchKernelGGL(k_pgo_linearize, dim3(lg), dim3(128), 0, st, d, T_meas, omega, T, p.huber_delta, !update);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+    }
+    if (update && d.m == 0) continue;
+    hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, d, T, p.lambda, it, update);
+    if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+  }
+  if (report) {
+    std::vector<double> chi(p.iters + 1, 0.0);
+    int32_t status = 0;
+    e = hipMemcpyAsync(chi.data(), d.chi2, sizeof(double) * (p.iters + 1), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(&status, d.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(last_hip, e);
+    memset(report, 0, sizeof(*report));
+    for (int i = 0; i < std::min(p.iters, 64); ++i) report->chi2[i] = chi[i];
+    report->final_chi2 = n_edges > 0 ? chi[p.iters] : 0.0;
+    report->status = status;
+    report->iters = p.iters;
+    report->factor_nnz_blocks = ws->nnz_blocks;
+  } else {
+    e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return fail(last_hip, e);
+  }
+  return S3A_OK;
+}
+
 }  // namespace s3a
