@@ -83,7 +83,7 @@ enum {
 #define S3A_FLAG_PLAIN 0x1u        /* one pair at a time, one launch per pass */
 #define S3A_FLAG_FINAL_COST 0x2u   /* one more pass: cost and inliers at the final iterate */
 #define S3A_FLAG_NO_GRAPH 0x4u     /* batched: launch directly, do not capture/replay a graph */
-#define S3A_FLAG_MULTI_LAUNCH 0x8u /* batched: one launch per pass instead of one persistent launch */
+#define S3A_FLAG_PERSISTENT 0x8u   /* batched: one persistent launch for all passes (see s3a_align_pairs) */
 
 /*
  * A batch of pairs in structure-of-arrays form: seven planes (px, py, pz,
@@ -134,10 +134,15 @@ int s3a_destroy(s3a_handle* h);
  *           or NULL for the weighted Umeyama closed form.
  *   S_out:  device, n_pairs results (the K-th Gauss-Newton iterate).
  *   info:   device, n_pairs diagnostics, or NULL.
- * Batched (default): all pairs together, one persistent launch captured in a
- * graph and replayed on later calls of the same shape. S3A_FLAG_PLAIN: one
- * pair at a time, one launch per pass; synchronises the stream once to read
- * the pair sizes.
+ * Batched (default): all pairs together; each pass is one launch over every
+ * tile of every pair plus one FP64 finalize launch, the whole sequence
+ * captured once in a graph and replayed on later calls of the same shape.
+ * S3A_FLAG_PERSISTENT: all passes in one persistent launch that hands out
+ * (pass, tile) work items in pass-major order and finalizes each pair when
+ * its last tile of a pass arrives (its per-item cross-workgroup release and
+ * acquire make it slower on multi-die parts; kept as an option).
+ * S3A_FLAG_PLAIN: one pair at a time, one launch per pass; synchronises the
+ * stream once to read the pair sizes.
  */
 int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* init,
                     s3a_sim3* S_out, s3a_align_info* info, s3a_stream stream);

@@ -14,7 +14,7 @@ LIB_PATH = os.path.join(HERE, "libs3a.so")
 F32, BF16 = 0, 1
 OK, EINVAL, EHIP, ENOMEM = 0, -1, -2, -3
 PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE, PAIR_ABORTED = range(6)
-FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_MULTI_LAUNCH = 0x1, 0x2, 0x4, 0x8
+FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 PGO_INIT_CHAIN = 0x1
 
 c_void_p = ctypes.c_void_p

@@ -14,8 +14,6 @@ using namespace s3a;
 
 namespace {
 
-constexpr bool kPersistentAvailable = true;
-
 struct GraphKey {
   int dtype, n_pairs, K, wg, items, occupancy, window, persistent;
   int64_t n_points;
@@ -173,7 +171,7 @@ int check_desc(const s3a_align_desc* d) {
   if (!(d->conf_threshold >= 0.0f)) return S3A_EINVAL;  // rejects NaN
   if (d->irls_iters < 0 || d->irls_iters > 10000) return S3A_EINVAL;
   if (!(d->huber_delta > 0.0)) return S3A_EINVAL;
-  if (d->flags & ~(S3A_FLAG_PLAIN | S3A_FLAG_FINAL_COST | S3A_FLAG_NO_GRAPH | S3A_FLAG_MULTI_LAUNCH))
+  if (d->flags & ~(S3A_FLAG_PLAIN | S3A_FLAG_FINAL_COST | S3A_FLAG_NO_GRAPH | S3A_FLAG_PERSISTENT))
     return S3A_EINVAL;
   if (d->reserved != 0) return S3A_EINVAL;
   return S3A_OK;
@@ -383,7 +381,7 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
     return S3A_OK;
   }
 
-  const bool persistent = kPersistentAvailable && !(d->flags & S3A_FLAG_MULTI_LAUNCH);
+  const bool persistent = (d->flags & S3A_FLAG_PERSISTENT) != 0;
   if ((d->flags & S3A_FLAG_NO_GRAPH) || h->timing) {
     S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
     S3A_TRY(enqueue_batched(h, d->dtype, lc, sh, dcd, persistent, st));
@@ -583,7 +581,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   const int wgs[2] = {256, 512};
   const int its[3] = {2, 4, 8};
   const int occs[3] = {2, 4, 8};
-  const bool persistent = !(d->flags & S3A_FLAG_MULTI_LAUNCH) && !(d->flags & S3A_FLAG_PLAIN);
+  const bool persistent = (d->flags & S3A_FLAG_PERSISTENT) && !(d->flags & S3A_FLAG_PLAIN);
   s3a_align_desc dd = *d;
   dd.flags &= ~S3A_FLAG_PLAIN;
   for (int wg : wgs)

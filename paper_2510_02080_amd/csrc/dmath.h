@@ -232,12 +232,13 @@ S3A_HD bool cholesky_solve_packed(double* L, const double* b, double* x) {
     for (int k = 0; k < j; ++k) d -= L[rj + k] * L[rj + k];
     if (!(d > 0.0)) return false;
     d = sqrt(d);
-    L[rj + j] = d;
+    const double inv = 1.0 / d;
+    L[rj + j] = inv;  // the diagonal is kept as its reciprocal
     for (int i = j + 1; i < N; ++i) {
       const int ri = i * (i + 1) / 2;
       double v = L[ri + j];
       for (int k = 0; k < j; ++k) v -= L[ri + k] * L[rj + k];
-      L[ri + j] = v / d;
+      L[ri + j] = v * inv;
     }
   }
   double y[N];
@@ -245,12 +246,12 @@ S3A_HD bool cholesky_solve_packed(double* L, const double* b, double* x) {
     const int ri = i * (i + 1) / 2;
     double v = b[i];
     for (int k = 0; k < i; ++k) v -= L[ri + k] * y[k];
-    y[i] = v / L[ri + i];
+    y[i] = v * L[ri + i];
   }
   for (int i = N - 1; i >= 0; --i) {
     double v = y[i];
     for (int k = i + 1; k < N; ++k) v -= L[k * (k + 1) / 2 + i] * x[k];
-    x[i] = v / L[i * (i + 1) / 2 + i];
+    x[i] = v * L[i * (i + 1) / 2 + i];
   }
   return true;
 }
@@ -271,6 +272,37 @@ S3A_HD double int_exp_pow(int n, double sg) {
   return F;
 }
 
+// Coefficients of the double series used for small steps (th = |omega| < 0.1,
+// |sigma| < 0.1), all from int_0^1 e^{sigma u} f(u th) du expanded in sigma
+// and th^2:
+//   A  = sin th / th            = sum_m (-1)^m th^{2m} / (2m+1)!
+//   B  = (1 - cos th) / th^2    = sum_m (-1)^m th^{2m} / (2m+2)!
+//   c1 = int e^{su} sin(u th)/th        = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+1)! k! (2m+k+2))
+//   c2 = int e^{su} (1-cos(u th))/th^2  = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+2)! k! (2m+k+3))
+//   a0 = int e^{su}                     = sum_k s^k / (k+1)!
+// Truncation at m < 5, k < 12 leaves terms below 1e-20.
+struct SmallStepSeries {
+  double c1[5][12], c2[5][12], a0[12], A[5], B[5];
+};
+
+constexpr SmallStepSeries make_small_step_series() {
+  SmallStepSeries t{};
+  double fact[40] = {};
+  fact[0] = 1.0;
+  for (int i = 1; i < 40; ++i) fact[i] = fact[i - 1] * i;
+  for (int m = 0; m < 5; ++m) {
+    const double sg = (m & 1) ? -1.0 : 1.0;
+    t.A[m] = sg / fact[2 * m + 1];
+    t.B[m] = sg / fact[2 * m + 2];
+    for (int k = 0; k < 12; ++k) {
+      t.c1[m][k] = sg / (fact[2 * m + 1] * fact[k] * (2 * m + k + 2));
+      t.c2[m][k] = sg / (fact[2 * m + 2] * fact[k] * (2 * m + k + 3));
+    }
+  }
+  for (int k = 0; k < 12; ++k) t.a0[k] = 1.0 / fact[k + 1];
+  return t;
+}
+
 // Rotation R = exp([omega]_x) (Rodrigues) and the translation map
 // V = int_0^1 e^{sigma u} exp(u [omega]_x) du = a0 I + c1 [omega]_x + c2 [omega]_x^2,
 // a0 = F_0(sigma), c1 = int e^{sigma u} sin(u th)/th du,
@@ -279,9 +311,24 @@ S3A_HD void sim3_RV(const double* w, double sg, double* R, double* V) {
   const double th2 = w[0] * w[0] + w[1] * w[1] + w[2] * w[2];
   const double th = sqrt(th2);
   double A, B;  // Rodrigues coefficients sin(th)/th, (1 - cos th)/th^2
-  double c1, c2;
-  const double a0 = int_exp_pow(0, sg);
-  if (th < 0.1) {
+  double c1, c2, a0;
+  if (th < 0.1 && fabs(sg) < 0.1) {
+    constexpr SmallStepSeries T = make_small_step_series();
+    A = 0.0; B = 0.0; c1 = 0.0; c2 = 0.0; a0 = 0.0;
+    for (int k = 11; k >= 0; --k) a0 = a0 * sg + T.a0[k];
+    for (int mm = 4; mm >= 0; --mm) {
+      double p1 = 0.0, p2 = 0.0;
+      for (int k = 11; k >= 0; --k) {
+        p1 = p1 * sg + T.c1[mm][k];
+        p2 = p2 * sg + T.c2[mm][k];
+      }
+      c1 = c1 * th2 + p1;
+      c2 = c2 * th2 + p2;
+      A = A * th2 + T.A[mm];
+      B = B * th2 + T.B[mm];
+    }
+  } else if (th < 0.1) {
+    a0 = int_exp_pow(0, sg);
     // series in th^2: sin(u th)/th = sum (-1)^k th^{2k} u^{2k+1}/(2k+1)!,
     // (1-cos(u th))/th^2 = sum (-1)^k th^{2k} u^{2k+2}/(2k+2)!
     A = 0.0; B = 0.0; c1 = 0.0; c2 = 0.0;
@@ -297,6 +344,7 @@ S3A_HD void sim3_RV(const double* w, double sg, double* R, double* V) {
       f2 *= (double)((2 * k + 3) * (2 * k + 4));
     }
   } else {
+    a0 = sg == 0.0 ? 1.0 : expm1(sg) / sg;
     const double sn = sin(th), cs = cos(th);
     A = sn / th;
     B = (1.0 - cs) / th2;

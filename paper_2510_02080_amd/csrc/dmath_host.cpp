@@ -45,6 +45,14 @@ int s3a_host_cholesky7(const double* H, const double* b, double* x) {
   return cholesky_solve<7>(Hc, b, x) ? 0 : 1;
 }
 
+int s3a_host_cholesky7_packed(const double* H, const double* b, double* x) {
+  double L[28];
+  int u = 0;
+  for (int i = 0; i < 7; ++i)
+    for (int j = 0; j <= i; ++j) L[u++] = H[7 * i + j];
+  return cholesky_solve_packed<7>(L, b, x) ? 0 : 1;
+}
+
 // moments: W, sp[3], sq[3], spp, sqp[9]
 int s3a_host_umeyama(const double* m, double* T) {
   Sim3d S;

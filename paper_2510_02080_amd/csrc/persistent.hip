@@ -61,12 +61,7 @@ __device__ inline uint32_t ld_acquire(const uint32_t* p) {
   return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// STATIC = 1: workgroup b takes tickets b, b + G, b + 2G, ... (G = grid size),
-// which keeps the pass-major order without a shared counter; the launch then
-// sizes the grid to the number of workgroups that can be resident at once
-// (every workgroup must be running for its tickets to progress).
-// STATIC = 0: tickets from one atomic counter (no residency requirement).
-template <int DT, int WG, int ITEMS, int STATIC>
+template <int DT, int WG, int ITEMS>
 __global__ __launch_bounds__(WG, 2) void k_persistent(Shape sh, const CallDesc* __restrict__ cd, Work w) {
   __shared__ double red[WG / 64][NSTAT];
   __shared__ unsigned long long s_ticket;
@@ -81,15 +76,10 @@ __global__ __launch_bounds__(WG, 2) void k_persistent(Shape sh, const CallDesc* 
 #pragma unroll
   for (int j = 0; j < 7; ++j) pl[j] = cd->planes[j];
 
-  for (uint64_t it = 0;; ++it) {
-    uint64_t x;
-    if constexpr (STATIC) {
-      x = (uint64_t)blockIdx.x + it * (uint64_t)gridDim.x;
-    } else {
-      if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1ull);
-      __syncthreads();
-      x = s_ticket;
-    }
+  for (;;) {
+    if (threadIdx.x == 0) s_ticket = atomicAdd(ticket, 1ull);
+    __syncthreads();
+    const uint64_t x = s_ticket;
     if (x >= total_tickets) break;
     const int pass = (int)(x / (uint64_t)total_tiles);
     const int t = (int)(x % (uint64_t)total_tiles);
@@ -147,19 +137,10 @@ __global__ __launch_bounds__(WG, 2) void k_persistent(Shape sh, const CallDesc* 
 template <int DT>
 static hipError_t launch_persistent_t(const LaunchCfg& lc, const Shape& sh, const CallDesc* cd, const Work& w,
                                       int grid, hipStream_t st) {
-  const int n_cu = grid / lc.occupancy;
-#define S3A_CASE(WGV, IT)                                                                                   \
-  if (lc.wg == WGV && lc.items == IT) {                                                                     \
-    if (lc.window == 0) {                                                                                   \
-      int nb = 0;                                                                                           \
-      hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<DT, WGV, IT, 1>, WGV, 0); \
-      if (e != hipSuccess) return e;                                                                        \
-      const int g = std::max(1, std::min(nb, lc.occupancy)) * n_cu;                                         \
-      hipLaunchKernelGGL((k_persistent<DT, WGV, IT, 1>), dim3(g), dim3(WGV), 0, st, sh, cd, w);            \
-    } else {                                                                                                \
-      hipLaunchKernelGGL((k_persistent<DT, WGV, IT, 0>), dim3(grid), dim3(WGV), 0, st, sh, cd, w);          \
-    }                                                                                                       \
-    return hipGetLastError();                                                                               \
+#define S3A_CASE(WGV, IT)                                                                   \
+  if (lc.wg == WGV && lc.items == IT) {                                                     \
+    hipLaunchKernelGGL((k_persistent<DT, WGV, IT>), dim3(grid), dim3(WGV), 0, st, sh, cd, w); \
+    return hipGetLastError();                                                               \
   }
   S3A_CASE(256, 2) S3A_CASE(256, 4) S3A_CASE(256, 8) S3A_CASE(512, 2) S3A_CASE(512, 4) S3A_CASE(512, 8)
 #undef S3A_CASE

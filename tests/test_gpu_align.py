@@ -32,7 +32,7 @@ def run(h, batch, flags=0, iters=None, init=None):
     return s3a.sim3_to_numpy(S), s3a.info_to_numpy(ib)
 
 
-@pytest.mark.parametrize("flags", [0, s3a.FLAG_PLAIN, s3a.FLAG_NO_GRAPH | s3a.FLAG_MULTI_LAUNCH])
+@pytest.mark.parametrize("flags", [0, s3a.FLAG_PLAIN, s3a.FLAG_NO_GRAPH, s3a.FLAG_PERSISTENT])
 def test_config0(h, flags):
     b = synth.config0()
     T, info = run(h, b, flags)
@@ -46,7 +46,7 @@ SIZES = [5000, 0, 1, 2, 3, 7, 100, 2047, 2048, 2049, 4096, 4097, 8191, 30001, 65
 SPECIALS = {15: "nan_all", 16: "nan_some", 17: "below_tau", 18: "collinear", 19: "coincident"}
 
 
-@pytest.mark.parametrize("flags", [0, s3a.FLAG_PLAIN, s3a.FLAG_FINAL_COST])
+@pytest.mark.parametrize("flags", [0, s3a.FLAG_PLAIN, s3a.FLAG_FINAL_COST, s3a.FLAG_PERSISTENT | s3a.FLAG_FINAL_COST])
 def test_ragged_and_degenerate(h, flags):
     b = ragged_batch(SIZES, seed=1, specials=SPECIALS)
     T, info = run(h, b, flags)
@@ -105,7 +105,7 @@ def test_bitwise_deterministic_and_graph_equals_direct(h):
     b = ragged_batch([70000, 3000, 150000, 12345], seed=5)
     pm = s3a.Pointmaps.from_batch(b, "cuda:0")
     outs = []
-    for flags in (0, 0, s3a.FLAG_NO_GRAPH, s3a.FLAG_NO_GRAPH | s3a.FLAG_MULTI_LAUNCH):
+    for flags in (0, 0, s3a.FLAG_NO_GRAPH, s3a.FLAG_PERSISTENT, s3a.FLAG_PERSISTENT | s3a.FLAG_NO_GRAPH):
         S, ib = h.align_pairs(pm, b.tau, b.delta, b.iters, flags=flags)
         torch.cuda.synchronize()
         outs.append((S.cpu().numpy().copy(), ib.cpu().numpy().copy()))

@@ -60,8 +60,9 @@ def test_exp_matches_oracle(lib):
     rng = np.random.default_rng(1)
     cases = [rand_xi(rng) for _ in range(200)]
     # small-angle, small-scale and mixed branches
-    cases += [np.array([0.3, -0.1, 0.2, a, -0.5 * a, 0.2 * a, sg]) for a in (0.0, 1e-9, 1e-5, 0.05, 0.0999, 0.1001)
-              for sg in (0.0, 1e-8, -3e-4, 0.7, 2.5, -3.1)]
+    cases += [np.array([0.3, -0.1, 0.2, a, -0.5 * a, 0.2 * a, sg])
+              for a in (0.0, 1e-9, 1e-5, 0.05, 0.0999 / 1.14, 0.1001 / 1.14, 0.5)
+              for sg in (0.0, 1e-8, -3e-4, 0.0999, -0.0999, 0.1001, -0.1001, 0.7, 2.5, -3.1)]
     for xi in cases:
         assert np.abs(c_exp(lib, xi) - sim3.exp(xi)).max() < 1e-12 * max(1.0, np.abs(sim3.exp(xi)).max())
 
@@ -114,9 +115,13 @@ def test_inv7_and_cholesky(lib):
         x = np.zeros(7)
         assert lib.s3a_host_cholesky7(ptr(np.ascontiguousarray(H)), ptr(b), ptr(x)) == 0
         assert np.allclose(H @ x, b, atol=1e-10)
+        x2 = np.zeros(7)
+        assert lib.s3a_host_cholesky7_packed(ptr(np.ascontiguousarray(H)), ptr(b), ptr(x2)) == 0
+        assert np.allclose(H @ x2, b, atol=1e-10)
     H = np.eye(7)
     H[3, 3] = -1.0
     assert lib.s3a_host_cholesky7(ptr(H), ptr(np.ones(7)), ptr(np.zeros(7))) == 1
+    assert lib.s3a_host_cholesky7_packed(ptr(H), ptr(np.ones(7)), ptr(np.zeros(7))) == 1
 
 
 def moments(p, q, w):
