@@ -144,7 +144,8 @@ static hipError_t launch_adjoint_t(const LaunchCfg& lc, const Shape& sh, const C
     hipLaunchKernelGGL((k_adjoint<DT, WGV, IT>), dim3(grid), dim3(WGV), 0, st, sh, cd, w); \
     return hipGetLastError();                                                            \
   }
-  S3A_CASE(256, 2) S3A_CASE(256, 4) S3A_CASE(256, 8) S3A_CASE(512, 2) S3A_CASE(512, 4) S3A_CASE(512, 8)
+  S3A_CASE(256, 2) S3A_CASE(256, 4) S3A_CASE(256, 8) S3A_CASE(256, 16)
+  S3A_CASE(512, 2) S3A_CASE(512, 4) S3A_CASE(512, 8)
 #undef S3A_CASE
   return hipErrorInvalidValue;
 }

@@ -158,7 +158,8 @@ static hipError_t launch_pass_t(const LaunchCfg& lc, const Shape& sh, const Call
     hipLaunchKernelGGL((k_pass<DT, MODE, WGV, IT>), dim3(grid), dim3(WGV), 0, st, sh, cd, w, tile_lo, tile_hi); \
     return hipGetLastError();                                                                               \
   }
-  S3A_CASE(256, 2) S3A_CASE(256, 4) S3A_CASE(256, 8) S3A_CASE(512, 2) S3A_CASE(512, 4) S3A_CASE(512, 8)
+  S3A_CASE(256, 2) S3A_CASE(256, 4) S3A_CASE(256, 8) S3A_CASE(256, 16)
+  S3A_CASE(512, 2) S3A_CASE(512, 4) S3A_CASE(512, 8)
 #undef S3A_CASE
   return hipErrorInvalidValue;
 }

@@ -21,6 +21,16 @@ namespace s3a {
 template <int DT>
 struct Planes;
 
+// The planes live in global memory: loads go through global (not flat)
+// address-space pointers.
+#if defined(__HIP_DEVICE_COMPILE__)
+#define S3A_GLOBAL __attribute__((address_space(1)))
+#else
+#define S3A_GLOBAL
+#endif
+typedef float s3a_f4 __attribute__((ext_vector_type(4)));
+typedef unsigned int s3a_u4 __attribute__((ext_vector_type(4)));
+
 template <>
 struct Planes<S3A_F32> {
   static constexpr int VEC = 4;
@@ -28,7 +38,7 @@ struct Planes<S3A_F32> {
     if (g0 + 4 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const float4 x = *reinterpret_cast<const float4*>(static_cast<const float*>(pl[j]) + g0);
+        const s3a_f4 x = *((const S3A_GLOBAL s3a_f4*)(static_cast<const float*>(pl[j]) + g0));
         v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
       }
     } else {
@@ -50,7 +60,7 @@ struct Planes<S3A_BF16> {
     if (g0 + 8 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const uint4 x = *reinterpret_cast<const uint4*>(static_cast<const uint16_t*>(pl[j]) + g0);
+        const s3a_u4 x = *((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(pl[j]) + g0));
         v[j][0] = lo(x.x); v[j][1] = hi(x.x); v[j][2] = lo(x.y); v[j][3] = hi(x.y);
         v[j][4] = lo(x.z); v[j][5] = hi(x.z); v[j][6] = lo(x.w); v[j][7] = hi(x.w);
       }
@@ -89,12 +99,17 @@ __device__ inline PointParams load_params(const PointParams* p) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) { r.M[i] = uniform_f64(p->M[i]); r.Mf[i] = uniform_f32(p->Mf[i]); }
 #pragma unroll
-  for (int i = 0; i < 3; ++i) { r.t[i] = uniform_f64(p->t[i]); r.c[i] = uniform_f64(p->c[i]); }
+  for (int i = 0; i < 3; ++i) {
+    r.t[i] = uniform_f64(p->t[i]);
+    r.c[i] = uniform_f64(p->c[i]);
+    r.tcf[i] = uniform_f32(p->tcf[i]);
+    r.cf[i] = uniform_f32(p->cf[i]);
+  }
   r.inv_C = uniform_f32(p->inv_C);
   r.scale = uniform_f32(p->scale);
   r.L = uniform_f32(p->L);
   r.active = uniform_i32(p->active);
-  r.pad = 0;
+  r.nonfinite = uniform_i32(p->nonfinite);
   return r;
 }
 
@@ -212,6 +227,55 @@ __device__ inline T wave_sum(T v) {
   return v;
 }
 
+// FP32 sums over the 64 lanes of a wavefront with DPP row operations (a fixed
+// pairwise tree: neighbours within quads, half rows, rows, then across rows;
+// the total ends in lane 63). All NSTAT sums advance one step at a time, so
+// consecutive DPP operations never read a register written just before.
+template <int N>
+__device__ inline void wave_totals_f32(float (&v)[N]) {
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // quad_perm [1,0,3,2]
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0xb1, 0xf, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // quad_perm [2,3,0,1]
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0x4e, 0xf, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // row_half_mirror
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0x141, 0xf, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // row_mirror
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0x140, 0xf, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // row_bcast:15 into rows 1 and 3
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0x142, 0xa, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j)  // row_bcast:31 into rows 2 and 3
+    v[j] += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v[j]), 0x143, 0xc, 0xf, false));
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v[j]), 63));
+}
+
+// Reduce NSTAT per-lane FP32 values over the workgroup (DPP within a
+// wavefront, then FP64 across wavefronts through LDS) and store one FP64
+// partial.
+template <int WG>
+__device__ inline void block_store_f32(float (&acc)[NSTAT], double (*red)[NSTAT], double* out) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_totals_f32(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < NSTAT; ++j) red[wv][j] = (double)acc[j];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < NSTAT) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < WG / 64; ++q) s += red[q][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+  __syncthreads();
+}
+
 // Reduce NSTAT per-lane values over the workgroup and store one FP64 partial.
 template <typename T, int WG>
 __device__ inline void block_store(T (&acc)[NSTAT], double (*red)[NSTAT], double* out, int nstat) {
@@ -235,9 +299,93 @@ __device__ inline void block_store(T (&acc)[NSTAT], double (*red)[NSTAT], double
 
 // ---------------------------------------------------------------- tile bodies
 
+// Gauss-Newton pass over one tile. Every quantity is formed in FP32 in
+// coordinates centred on the pair's centre c (the weighted target centroid):
+//   y_c = Mf p + (t - c),  q_c = q - c,  r = y_c - q_c,
+// so no product or difference involves coordinates far from the data, and the
+// 17 statistics plus cost and inlier count accumulate per lane over the few
+// points the lane handles in this tile (then pairwise across lanes, FP64
+// across wavefronts and tiles). Points outside the pair's range, below the
+// confidence threshold, or (in pairs that hold any) with a NaN/Inf value get
+// zero weight and zeroed coordinates.
+template <int DT, int WG, int ITEMS>
+__device__ inline void tile_gn(const Shape& sh, const void* const* pl, const TileDesc& td, const PointParams& P,
+                               double (*red)[NSTAT], double* out) {
+  constexpr int VEC = Planes<DT>::VEC;
+  float a[NSTAT];
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) a[j] = 0.0f;
+  if (P.active) {
+    const float tau = sh.tau, delta = sh.delta_f;
+    const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
+    const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+    const bool check_finite = P.nonfinite != 0;
+#pragma unroll 1
+    for (int it = 0; it < ITEMS; ++it) {
+      const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+      if (rel0 >= end_rel) break;
+      float v[7][VEC];
+      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+      if (rel0 < lo_rel || rel0 + VEC > end_rel) {  // boundary vector: zero foreign elements
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
+#pragma unroll
+          for (int j = 0; j < 7; ++j) v[j][e] = in ? v[j][e] : 0.0f;
+        }
+      }
+      if (check_finite) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          float x[7];
+#pragma unroll
+          for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+          const bool fin = finite7(x);
+#pragma unroll
+          for (int j = 0; j < 7; ++j) v[j][e] = fin ? v[j][e] : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const float px = v[0][e], py = v[1][e], pz = v[2][e];
+        const float w = v[6][e] >= tau ? v[6][e] : 0.0f;
+        const float y0 = fmaf(P.Mf[0], px, fmaf(P.Mf[1], py, fmaf(P.Mf[2], pz, P.tcf[0])));
+        const float y1 = fmaf(P.Mf[3], px, fmaf(P.Mf[4], py, fmaf(P.Mf[5], pz, P.tcf[1])));
+        const float y2 = fmaf(P.Mf[6], px, fmaf(P.Mf[7], py, fmaf(P.Mf[8], pz, P.tcf[2])));
+        const float r0 = y0 - (v[3][e] - P.cf[0]);
+        const float r1 = y1 - (v[4][e] - P.cf[1]);
+        const float r2 = y2 - (v[5][e] - P.cf[2]);
+        const float e2 = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+        const float ie = __builtin_amdgcn_rsqf(e2);
+        const bool inl = e2 <= d2;
+        const float psi = inl ? 1.0f : delta * ie;
+        const float rho = inl ? 0.5f * e2 : fmaf(delta * e2, ie, -hd2);
+        const float om = w * psi;
+        const float oy0 = om * y0, oy1 = om * y1, oy2 = om * y2;
+        a[0] += om;
+        a[1] += oy0; a[2] += oy1; a[3] += oy2;
+        a[4] = fmaf(oy0, y0, a[4]); a[5] = fmaf(oy0, y1, a[5]); a[6] = fmaf(oy0, y2, a[6]);
+        a[7] = fmaf(oy1, y1, a[7]); a[8] = fmaf(oy1, y2, a[8]); a[9] = fmaf(oy2, y2, a[9]);
+        a[10] = fmaf(om, r0, a[10]); a[11] = fmaf(om, r1, a[11]); a[12] = fmaf(om, r2, a[12]);
+        a[13] = fmaf(oy1, r2, fmaf(-oy2, r1, a[13]));
+        a[14] = fmaf(oy2, r0, fmaf(-oy0, r2, a[14]));
+        a[15] = fmaf(oy0, r1, fmaf(-oy1, r0, a[15]));
+        a[16] = fmaf(oy0, r0, fmaf(oy1, r1, fmaf(oy2, r2, a[16])));
+        a[17] = fmaf(w, rho, a[17]);
+        a[18] += (inl && w > 0.0f) ? 1.0f : 0.0f;
+      }
+    }
+  }
+  block_store_f32<WG>(a, red, out);
+}
+
 template <int DT, int MODE, int WG, int ITEMS>
 __device__ inline void tile_body(const Shape& sh, const void* const* pl, const TileDesc& td,
                                  const PointParams& P, double (*red)[NSTAT], double* out) {
+  if constexpr (MODE == MODE_GN) {
+    tile_gn<DT, WG, ITEMS>(sh, pl, td, P, red, out);
+    return;
+  }
   constexpr int VEC = Planes<DT>::VEC;
   using Acc = typename std::conditional<MODE == MODE_GN, float, double>::type;
   Acc acc[NSTAT];

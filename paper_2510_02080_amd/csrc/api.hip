@@ -204,7 +204,8 @@ LaunchCfg pick_cfg(s3a_handle* h, int dtype, int64_t n_points) {
 }
 
 bool valid_cfg(const LaunchCfg& c) {
-  return (c.wg == 256 || c.wg == 512) && (c.items == 2 || c.items == 4 || c.items == 8) && c.occupancy >= 1 &&
+  return (c.wg == 256 || c.wg == 512) && (c.items == 2 || c.items == 4 || c.items == 8 || (c.items == 16 && c.wg == 256)) &&
+         c.occupancy >= 1 &&
          c.occupancy <= 8 && c.window >= 0;
 }
 
@@ -579,7 +580,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   LaunchCfg bestc = default_cfg(d->dtype);
   float best_ms = 1e30f;
   const int wgs[2] = {256, 512};
-  const int its[3] = {2, 4, 8};
+  const int its[4] = {2, 4, 8, 16};
   const int occs[3] = {2, 4, 8};
   const bool persistent = (d->flags & S3A_FLAG_PERSISTENT) && !(d->flags & S3A_FLAG_PLAIN);
   s3a_align_desc dd = *d;
@@ -587,7 +588,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   for (int wg : wgs)
     for (int it : its)
       for (int oc : occs) {
-        if (wg == 512 && oc > 4) continue;
+        if (wg == 512 && (oc > 4 || it > 8)) continue;
         if (!persistent && oc != 4) continue;
         LaunchCfg c;
         c.wg = wg;

@@ -30,15 +30,20 @@ __device__ inline bool sim3_finite(const Sim3d& S) {
   return f;
 }
 
-__device__ inline void publish(PointParams* P, const Sim3d& S, const double* c, int active) {
+__device__ inline void publish(PointParams* P, const Sim3d& S, const double* c, int active, int nonfinite = 1) {
   PointParams p;
   for (int i = 0; i < 9; ++i) { p.M[i] = S.s * S.R[i]; p.Mf[i] = (float)p.M[i]; }
-  for (int i = 0; i < 3; ++i) { p.t[i] = S.t[i]; p.c[i] = c[i]; }
+  for (int i = 0; i < 3; ++i) {
+    p.t[i] = S.t[i];
+    p.c[i] = c[i];
+    p.tcf[i] = (float)(S.t[i] - c[i]);
+    p.cf[i] = (float)c[i];
+  }
   p.inv_C = 0.0f;
   p.scale = 0.0f;
   p.L = 0.0f;
   p.active = active;
-  p.pad = 0;
+  p.nonfinite = nonfinite;
   *P = p;
 }
 
@@ -120,7 +125,7 @@ __device__ inline void finalize_moments(const Shape& sh, const CallDesc* cd, Wor
   st->status = status;
   const bool more = status == S3A_PAIR_OK && (sh.K > 0 || (sh.flags & S3A_FLAG_FINAL_COST));
   if (!more) write_outputs(cd, k, *st, nan, 0);
-  publish(w.params + k, S, cq, more ? 1 : 0);
+  publish(w.params + k, S, cq, more ? 1 : 0, st->nnf > 0 ? 1 : 0);
 }
 
 // Gauss-Newton pass `pass` (1..K): assemble H, g in centred coordinates from the
@@ -183,7 +188,7 @@ __device__ inline void finalize_gn(const Shape& sh, const CallDesc* cd, Work& w,
   const bool last = pass == sh.K;
   const bool final_pass = (sh.flags & S3A_FLAG_FINAL_COST) != 0;
   if (failed || (last && !final_pass)) write_outputs(cd, k, *st, nan, 0);
-  publish(w.params + k, st->S, c, (failed || (last && !final_pass)) ? 0 : 1);
+  publish(w.params + k, st->S, c, (failed || (last && !final_pass)) ? 0 : 1, st->nnf > 0 ? 1 : 0);
 }
 
 __device__ inline void finalize_final_cost(const CallDesc* cd, Work& w, int k, const double* s) {

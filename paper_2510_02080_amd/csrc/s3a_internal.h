@@ -48,12 +48,14 @@ struct PointParams {
   double M[9];   // s R (FP64), y = M p + t
   double t[3];
   double c[3];   // centre of the Gauss-Newton statistics
-  float Mf[9];   // s R (FP32), for gradients w.r.t. p
+  float Mf[9];   // s R (FP32)
+  float tcf[3];  // t - c (FP32): centred model point y_c = Mf p + tcf
+  float cf[3];   // c (FP32): centred target q_c = q - cf
   float inv_C;   // 1 / C (adjoint)
   float scale;   // gL (adjoint)
   float L;       // cost (adjoint)
   int32_t active;// 0: skip (pair failed or finished)
-  int32_t pad;
+  int32_t nonfinite; // the pair holds NaN/Inf values (validity then checks finiteness)
 };
 
 // FP64 master state per pair.

@@ -11,6 +11,16 @@ TOL_ROT = 1e-5      # rad
 TOL_SCALE = 1e-5    # relative
 TOL_TRANS = 1e-5    # relative to max(|t|, 1 m)
 
+# The Gauss-Newton passes form each residual r_i = S p_i - q_i in FP32 (in
+# coordinates centred on the pair's target centroid): a few roundings of
+# intermediates no larger than EXTENT (the synthetic scenes stay within 40 m of
+# that centre), so |dr_i| <= 8 * 2^-24 * EXTENT. The reported cost
+# L = sum w rho(e_i) then moves by at most sum w e_i |dr_i| <= sqrt(2 L) * that
+# (Huber: |rho'| <= e), on top of summation error; the pose, a weighted
+# average over all points, is far less sensitive.
+EXTENT = 40.0
+DR = 8 * 2.0 ** -24 * EXTENT
+
 
 def ragged_batch(sizes, seed=0, tau=1.5, outlier_frac=0.1, specials=None):
     """Pairs of the given point counts, frustum geometry as the config-0 recipe
@@ -64,8 +74,9 @@ def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where=""):
     assert abs(info["weight_sum"] - ref["C"]) <= 1e-12 * ref["C"], where
     K = len(ref["costs"])
     if K:
-        assert abs(info["cost"] - ref["costs"][-1]) <= 1e-5 * abs(ref["costs"][-1]) + 1e-12, where
-        assert abs(int(info["n_inliers"]) - ref["inliers"][-1]) <= max(2, 1e-5 * ref["V"]), where
+        L = ref["costs"][-1]
+        assert abs(info["cost"] - L) <= 1e-5 * abs(L) + np.sqrt(2 * abs(L)) * DR, where
+        assert abs(int(info["n_inliers"]) - ref["inliers"][-1]) <= max(3, 1e-4 * ref["V"]), where
         Hr = ref["H"] / 1.0
         Hu = Hr[np.triu_indices(7)]
         sc = np.abs(Hr).max()

@@ -10,7 +10,7 @@ import torch
 import synth
 from oracle import irls
 
-from gpu_util import check_pair, ragged_batch
+from gpu_util import DR, check_pair, ragged_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -55,7 +55,8 @@ def test_ragged_and_degenerate(h, flags):
         ref = irls.irls_align(p, q, c, b.tau, b.delta, b.iters)
         check_pair(T[k], info[k], ref, where=f"pair {k} (n={SIZES[k]}, {SPECIALS.get(k)})")
         if flags & s3a.FLAG_FINAL_COST and ref["status"] == 0:
-            assert abs(info[k]["final_cost"] - ref["final_cost"]) <= 1e-5 * ref["final_cost"]
+            Lf = ref["final_cost"]
+            assert abs(info[k]["final_cost"] - Lf) <= 1e-5 * Lf + np.sqrt(2 * Lf) * DR
         else:
             assert np.isnan(info[k]["final_cost"])
     st = info["status"]
