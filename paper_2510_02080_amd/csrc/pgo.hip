@@ -52,8 +52,11 @@ struct PgoDev {
   // updates: target t (0..m-1 diagonal of position t, m + b off-diagonal block b) gets
   // -= L_a L_b^T for (a, b) in up_a/up_b[up_ptr[t]..]; a, b index blocks (always off-diagonal)
   const int32_t* up_ptr; const int32_t* up_a; const int32_t* up_b;
-  // level schedule (from the leaves)
+  // level schedule (from the leaves): columns, and per level the flattened
+  // update targets (diagonal c or m + off-diagonal block) and off-diagonal blocks
   const int32_t* lev_ptr; const int32_t* lev_col;
+  const int32_t* lt_ptr; const int32_t* lt_tgt;
+  const int32_t* lb_ptr; const int32_t* lb_blk;
   // rows of L for the forward solve: blocks (c, k), k < c
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
@@ -203,21 +206,19 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
   // ---- factorisation, level by level
   for (int l = 0; l < d.nlev; ++l) {
     const int c0 = d.lev_ptr[l], c1 = d.lev_ptr[l + 1];
-    // (A) targets of this level's columns: diagonal blocks and off-diagonal blocks,
-    // one lane per element: S -= sum_k L_a L_b^T
-    for (int cc = c0; cc < c1; ++cc) {
-      const int c = d.lev_col[cc];
-      const int nb = d.col_ptr[c + 1] - d.col_ptr[c];
-      for (int x = tid; x < (nb + 1) * 49; x += PGO_WG) {
-        const int tb = x / 49, a = x % 49, r = a / 7, s = a % 7;
-        const int target = tb == 0 ? c : d.m + d.col_ptr[c] + tb - 1;
+    // (A) every update target of this level (diagonal and off-diagonal blocks of
+    // its columns), one lane per element: S -= sum_k L_a L_b^T
+    {
+      const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
+      for (int x = tid; x < nt * 49; x += PGO_WG) {
+        const int target = d.lt_tgt[t0 + x / 49], a = x % 49, r = a / 7, s = a % 7;
         double acc = 0.0;
         for (int q = d.up_ptr[target]; q < d.up_ptr[target + 1]; ++q) {
-          const double* La = d.Lb + 49 * d.up_a[q];
-          const double* Lc = d.Lb + 49 * d.up_b[q];
-          for (int u = 0; u < 7; ++u) acc += La[7 * r + u] * Lc[7 * s + u];
+          const double* La = d.Lb + 49 * d.up_a[q] + 7 * r;
+          const double* Lc = d.Lb + 49 * d.up_b[q] + 7 * s;
+          for (int u = 0; u < 7; ++u) acc += La[u] * Lc[u];
         }
-        double* dst = tb == 0 ? d.Ld + 49 * c + a : d.Lb + 49 * (d.col_ptr[c] + tb - 1) + a;
+        double* dst = target < d.m ? d.Ld + 49 * target + a : d.Lb + 49 * (target - d.m) + a;
         *dst -= acc;
       }
     }
@@ -244,13 +245,13 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     }
     __syncthreads();
     if (s_fail) break;
-    // (C) L_ij = S_ij L_jj^{-T}: one lane per block row
-    for (int cc = c0; cc < c1; ++cc) {
-      const int c = d.lev_col[cc];
-      const double* D = d.Ld + 49 * c;
-      const int b0 = d.col_ptr[c], nb = d.col_ptr[c + 1] - b0;
+    // (C) L_ij = S_ij L_jj^{-T} for every off-diagonal block of this level: one lane per block row
+    {
+      const int b0 = d.lb_ptr[l], nb = d.lb_ptr[l + 1] - b0;
       for (int x = tid; x < nb * 7; x += PGO_WG) {
-        double* row = d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7);
+        const int b = d.lb_blk[b0 + x / 7];
+        const double* D = d.Ld + 49 * d.blk_col[b];
+        double* row = d.Lb + 49 * b + 7 * (x % 7);
         double y[7];
         for (int j = 0; j < 7; ++j) {
           double v = row[j];
@@ -344,7 +345,7 @@ namespace {
 struct Symbolic {
   int m = 0, nblk = 0, nlev = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
-      up_ptr, up_a, up_b, lev_ptr, lev_col, row_ptr, row_blk, chain;
+      up_ptr, up_a, up_b, lev_ptr, lev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk, chain;
   std::vector<int8_t> gv_sign;
 };
 
@@ -474,6 +475,20 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   S.lev_col.resize(m);
   std::vector<int> fill(S.lev_ptr.begin(), S.lev_ptr.end() - 1);
   for (int c = 0; c < m; ++c) S.lev_col[fill[lev[c]]++] = c;
+  S.lt_ptr.assign(nlev + 1, 0);
+  S.lb_ptr.assign(nlev + 1, 0);
+  for (int l = 0; l < nlev; ++l) {
+    for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
+      const int c = S.lev_col[q];
+      S.lt_tgt.push_back(c);
+      for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) {
+        S.lt_tgt.push_back(m + b);
+        S.lb_blk.push_back(b);
+      }
+    }
+    S.lt_ptr[l + 1] = (int32_t)S.lt_tgt.size();
+    S.lb_ptr[l + 1] = (int32_t)S.lb_blk.size();
+  }
   // rows of L (blocks (c, k), k < c) for the forward solve
   std::vector<std::vector<int>> rows(m);
   for (int b = 0; b < S.nblk; ++b) rows[S.blk_row[b]].push_back(b);
@@ -567,6 +582,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.gv_ptr.size()) + bytes_of<int32_t>(S.gv_edge.size()) + bytes_of<int8_t>(S.gv_sign.size());
     total += bytes_of<int32_t>(S.up_ptr.size()) + bytes_of<int32_t>(S.up_a.size()) * 2;
     total += bytes_of<int32_t>(S.lev_ptr.size()) + bytes_of<int32_t>(S.lev_col.size());
+    total += bytes_of<int32_t>(S.lt_ptr.size()) + bytes_of<int32_t>(S.lt_tgt.size());
+    total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.chain.size() + 4);
     total += bytes_of<double>(49 * (size_t)m) + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
@@ -609,6 +626,10 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_upb = carve<int32_t>(c, S.up_b.size()); put(p_upb, S.up_b); d.up_b = p_upb;
     int32_t* p_lvp = carve<int32_t>(c, S.lev_ptr.size()); put(p_lvp, S.lev_ptr); d.lev_ptr = p_lvp;
     int32_t* p_lvc = carve<int32_t>(c, S.lev_col.size()); put(p_lvc, S.lev_col); d.lev_col = p_lvc;
+    int32_t* p_ltp = carve<int32_t>(c, S.lt_ptr.size()); put(p_ltp, S.lt_ptr); d.lt_ptr = p_ltp;
+    int32_t* p_ltt = carve<int32_t>(c, S.lt_tgt.size()); put(p_ltt, S.lt_tgt); d.lt_tgt = p_ltt;
+    int32_t* p_lbp = carve<int32_t>(c, S.lb_ptr.size()); put(p_lbp, S.lb_ptr); d.lb_ptr = p_lbp;
+    int32_t* p_lbb = carve<int32_t>(c, S.lb_blk.size() + 1); put(p_lbb, S.lb_blk); d.lb_blk = p_lbb;
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
     int32_t* p_rwb = carve<int32_t>(c, S.row_blk.size()); put(p_rwb, S.row_blk); d.row_blk = p_rwb;
     int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
