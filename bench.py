@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--legs", default="bf16,plain,adjoint,pgo", help="comma list of extra legs")
     ap.add_argument("--verify", default="all", choices=["all", "sample", "none"])
     ap.add_argument("--workers", type=int, default=16)
+    ap.add_argument("--tuning", default="", help="force the launch shape wg,items,occupancy (skips autotuning)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run one plain 1 GiB device-to-device copy (known-size kernel for counter scaling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the alignment shards by pair "
@@ -95,6 +98,12 @@ def main():
     dev = "cuda:0"
     h = s3a.Handle(0)
     res = {}
+    if args.calib_copy:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)  # 1 GiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     def timed(fn, steps, warmup):
         for _ in range(warmup):
@@ -137,7 +146,11 @@ def main():
     # ---- headline: batched FP32, graph of per-pass launches
     pm = s3a.Pointmaps.from_batch(b2, dev)
     tune = None
-    if not args.no_autotune:
+    if args.tuning:
+        wg, it, oc = (int(x) for x in args.tuning.split(","))
+        h.set_tuning(s3a.F32, wg, it, oc)
+        tune = dict(wg=wg, items=it, occupancy=oc, window=0, forced=True)
+    elif not args.no_autotune:
         t = time.perf_counter()
         tune = h.autotune(pm, b2.tau, b2.delta, b2.iters)
         log(f"autotune {tune} in {time.perf_counter() - t:.1f}s")

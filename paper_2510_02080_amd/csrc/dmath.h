@@ -13,8 +13,10 @@
 
 #if defined(__HIPCC__) || defined(__HIP__)
 #define S3A_HD __host__ __device__ inline
+#define S3A_NO_UNROLL _Pragma("unroll 1")
 #else
 #define S3A_HD inline
+#define S3A_NO_UNROLL
 #endif
 
 namespace s3a {
@@ -303,6 +305,15 @@ constexpr SmallStepSeries make_small_step_series() {
   return t;
 }
 
+// The table lives in read-only memory and is walked by loops that are not
+// unrolled, so its 142 coefficients are loaded as needed instead of being
+// materialised in registers.
+#if defined(__HIPCC__) || defined(__HIP__)
+__device__ __constant__ constexpr SmallStepSeries kSmallStep = make_small_step_series();
+#else
+constexpr SmallStepSeries kSmallStep = make_small_step_series();
+#endif
+
 // Rotation R = exp([omega]_x) (Rodrigues) and the translation map
 // V = int_0^1 e^{sigma u} exp(u [omega]_x) du = a0 I + c1 [omega]_x + c2 [omega]_x^2,
 // a0 = F_0(sigma), c1 = int e^{sigma u} sin(u th)/th du,
@@ -313,11 +324,14 @@ S3A_HD void sim3_RV(const double* w, double sg, double* R, double* V) {
   double A, B;  // Rodrigues coefficients sin(th)/th, (1 - cos th)/th^2
   double c1, c2, a0;
   if (th < 0.1 && fabs(sg) < 0.1) {
-    constexpr SmallStepSeries T = make_small_step_series();
+    const SmallStepSeries& T = kSmallStep;
     A = 0.0; B = 0.0; c1 = 0.0; c2 = 0.0; a0 = 0.0;
+    S3A_NO_UNROLL
     for (int k = 11; k >= 0; --k) a0 = a0 * sg + T.a0[k];
+    S3A_NO_UNROLL
     for (int mm = 4; mm >= 0; --mm) {
       double p1 = 0.0, p2 = 0.0;
+      S3A_NO_UNROLL
       for (int k = 11; k >= 0; --k) {
         p1 = p1 * sg + T.c1[mm][k];
         p2 = p2 * sg + T.c2[mm][k];

@@ -207,41 +207,62 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
   for (int l = 0; l < d.nlev; ++l) {
     const int c0 = d.lev_ptr[l], c1 = d.lev_ptr[l + 1];
     // (A) every update target of this level (diagonal and off-diagonal blocks of
-    // its columns), one lane per element: S -= sum_k L_a L_b^T
+    // its columns): one wavefront per target, lane = element (r, s) of the 7x7
+    // block: S -= sum_k L_a L_b^T over the target's update list (in order; two
+    // updates in flight so their loads overlap).
     {
       const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
-      for (int x = tid; x < nt * 49; x += PGO_WG) {
-        const int target = d.lt_tgt[t0 + x / 49], a = x % 49, r = a / 7, s = a % 7;
-        double acc = 0.0;
-        for (int q = d.up_ptr[target]; q < d.up_ptr[target + 1]; ++q) {
-          const double* La = d.Lb + 49 * d.up_a[q] + 7 * r;
-          const double* Lc = d.Lb + 49 * d.up_b[q] + 7 * s;
-          for (int u = 0; u < 7; ++u) acc += La[u] * Lc[u];
+      const int lane = tid & 63, wv = tid >> 6;
+      const int r = lane / 7, s = lane % 7;
+      for (int ti = wv; ti < nt; ti += PGO_WG / 64) {
+        const int target = d.lt_tgt[t0 + ti];
+        const int q0 = d.up_ptr[target], q1 = d.up_ptr[target + 1];
+        double acc0 = 0.0, acc1 = 0.0;
+        if (lane < 49) {
+          int q = q0;
+          for (; q + 2 <= q1; q += 2) {
+            const double* A0 = d.Lb + 49 * d.up_a[q] + 7 * r;
+            const double* B0 = d.Lb + 49 * d.up_b[q] + 7 * s;
+            const double* A1 = d.Lb + 49 * d.up_a[q + 1] + 7 * r;
+            const double* B1 = d.Lb + 49 * d.up_b[q + 1] + 7 * s;
+            for (int u = 0; u < 7; ++u) {
+              acc0 += A0[u] * B0[u];
+              acc1 += A1[u] * B1[u];
+            }
+          }
+          if (q < q1) {
+            const double* A0 = d.Lb + 49 * d.up_a[q] + 7 * r;
+            const double* B0 = d.Lb + 49 * d.up_b[q] + 7 * s;
+            for (int u = 0; u < 7; ++u) acc0 += A0[u] * B0[u];
+          }
+          double* dst = target < d.m ? d.Ld + 49 * target + lane : d.Lb + 49 * (target - d.m) + lane;
+          *dst -= acc0 + acc1;
         }
-        double* dst = target < d.m ? d.Ld + 49 * target + a : d.Lb + 49 * (target - d.m) + a;
-        *dst -= acc;
       }
     }
     __syncthreads();
-    // (B) dense Cholesky of each diagonal block of the level (one lane per column)
-    for (int cc = c0 + tid; cc < c1; cc += PGO_WG) {
-      double* D = d.Ld + 49 * d.lev_col[cc];
-      bool ok = true;
-      for (int j = 0; j < 7 && ok; ++j) {
-        double s = D[8 * j];
-        for (int k = 0; k < j; ++k) s -= D[7 * j + k] * D[7 * j + k];
-        if (!(s > 0.0)) { ok = false; break; }
-        s = sqrt(s);
-        D[8 * j] = s;
-        for (int i = j + 1; i < 7; ++i) {
-          double v = D[7 * i + j];
-          for (int k = 0; k < j; ++k) v -= D[7 * i + k] * D[7 * j + k];
-          D[7 * i + j] = v / s;
+    // (B) Cholesky of each diagonal block of the level: one wavefront per block,
+    // lane 7r + s holds element (r, s) in a register; column j is scaled and
+    // broadcast by cross-lane reads, then the trailing elements are updated.
+    {
+      const int lane = tid & 63, wv = tid >> 6;
+      const int r = lane / 7, s = lane % 7;
+      for (int cc = c0 + wv; cc < c1; cc += PGO_WG / 64) {
+        double* D = d.Ld + 49 * d.lev_col[cc];
+        double a = lane < 49 ? D[lane] : 0.0;
+        bool ok = true;
+        for (int j = 0; j < 7; ++j) {
+          const double djj = __shfl(a, 8 * j, 64);
+          if (!(djj > 0.0)) { ok = false; break; }
+          const double ljj = sqrt(djj);
+          if (lane < 49 && s == j) a = r == j ? ljj : (r > j ? a / ljj : a);
+          const double lrj = __shfl(a, lane < 49 ? 7 * r + j : 0, 64);
+          const double lsj = __shfl(a, lane < 49 ? 7 * s + j : 0, 64);
+          if (lane < 49 && s > j && r >= s) a -= lrj * lsj;
         }
+        if (lane < 49) D[lane] = s > r ? 0.0 : a;
+        if (!ok && lane == 0) s_fail = 1;
       }
-      for (int i = 0; i < 7; ++i)
-        for (int j = i + 1; j < 7; ++j) D[7 * i + j] = 0.0;
-      if (!ok) s_fail = 1;
     }
     __syncthreads();
     if (s_fail) break;
