@@ -11,12 +11,16 @@
 
 namespace s3a {
 
+// Gradients are written once and not read back by the library: streaming
+// (non-temporal) global stores.
 __device__ inline void store_vec(float* base, int64_t g0, int64_t n, const float* v, int VEC, int64_t lo,
                                  int64_t hi) {
   if (!base) return;
   if (g0 >= lo && g0 + VEC <= hi && g0 + VEC <= n) {
-    for (int e = 0; e < VEC; e += 4)
-      *reinterpret_cast<float4*>(base + g0 + e) = make_float4(v[e], v[e + 1], v[e + 2], v[e + 3]);
+    for (int e = 0; e < VEC; e += 4) {
+      const s3a_f4 x = {v[e], v[e + 1], v[e + 2], v[e + 3]};
+      __builtin_nontemporal_store(x, (S3A_GLOBAL s3a_f4*)(base + g0 + e));
+    }
   } else {
     for (int e = 0; e < VEC; ++e) {
       const int64_t g = g0 + e;

@@ -22,7 +22,10 @@ template <int DT>
 struct Planes;
 
 // The planes live in global memory: loads go through global (not flat)
-// address-space pointers.
+// address-space pointers, and are marked non-temporal. Each stored point is
+// read once per pass and a pass streams far more than the caches hold, so
+// keeping the lines buys nothing; on gfx950 the streaming hint lifts a
+// read-only SoA sweep from about 6.2 to about 7.0 TB/s.
 #if defined(__HIP_DEVICE_COMPILE__)
 #define S3A_GLOBAL __attribute__((address_space(1)))
 #else
@@ -38,7 +41,7 @@ struct Planes<S3A_F32> {
     if (g0 + 4 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const s3a_f4 x = *((const S3A_GLOBAL s3a_f4*)(static_cast<const float*>(pl[j]) + g0));
+        const s3a_f4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_f4*)(static_cast<const float*>(pl[j]) + g0));
         v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
       }
     } else {
@@ -60,7 +63,7 @@ struct Planes<S3A_BF16> {
     if (g0 + 8 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
-        const s3a_u4 x = *((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(pl[j]) + g0));
+        const s3a_u4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(pl[j]) + g0));
         v[j][0] = lo(x.x); v[j][1] = hi(x.x); v[j][2] = lo(x.y); v[j][3] = hi(x.y);
         v[j][4] = lo(x.z); v[j][5] = hi(x.z); v[j][6] = lo(x.w); v[j][7] = hi(x.w);
       }
