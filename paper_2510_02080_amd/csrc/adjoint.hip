@@ -42,9 +42,9 @@ __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __rest
   for (int t = (int)blockIdx.x; t < total; t += (int)gridDim.x) {
     const TileDesc td = load_tile(w.tiles + t);
     const PointParams P = load_params(w.params + td.pair);
-    double acc[NSTAT];
+    double acc[7];
 #pragma unroll
-    for (int j = 0; j < NSTAT; ++j) acc[j] = 0.0;
+    for (int j = 0; j < 7; ++j) acc[j] = 0.0;
 #pragma unroll 1
     for (int it = 0; it < ITEMS; ++it) {
       const int64_t g0 = td.begin + (int64_t)(it * WG + (int)threadIdx.x) * VEC;
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __rest
 #pragma unroll
       for (int j = 0; j < 7; ++j) store_vec(gout[j], g0, sh.n_points, go[j], VEC, td.lo, td.end);
     }
-    block_store<double, WG>(acc, red, w.partials + (int64_t)t * NSTAT, 7);
+    block_store_f64<WG, 7>(acc, red, w.partials + (int64_t)t * NSTAT);
   }
 }
 

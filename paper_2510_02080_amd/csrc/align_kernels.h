@@ -129,27 +129,6 @@ __device__ inline TileDesc load_tile(const TileDesc* p) {
 
 // ---------------------------------------------------------------- per-point terms
 
-// Closed-form start: weighted raw moments, accumulated in FP64 (the products
-// of FP32 inputs are exact or nearly so in FP64).
-__device__ inline void point_moments(double (&a)[NSTAT], const float* x, bool in, float tau) {
-  const bool fin = finite7(x);
-  const bool valid = in && fin && x[6] >= tau;
-  const double w = valid ? (double)x[6] : 0.0;
-  const double p0 = valid ? (double)x[0] : 0.0, p1 = valid ? (double)x[1] : 0.0, p2 = valid ? (double)x[2] : 0.0;
-  const double q0 = valid ? (double)x[3] : 0.0, q1 = valid ? (double)x[4] : 0.0, q2 = valid ? (double)x[5] : 0.0;
-  const double wp0 = w * p0, wp1 = w * p1, wp2 = w * p2;
-  const double wq0 = w * q0, wq1 = w * q1, wq2 = w * q2;
-  a[0] += w;
-  a[1] += wp0; a[2] += wp1; a[3] += wp2;
-  a[4] += wq0; a[5] += wq1; a[6] += wq2;
-  a[7] = fma(wp0, p0, fma(wp1, p1, fma(wp2, p2, a[7])));
-  a[8] = fma(wq0, p0, a[8]);  a[9] = fma(wq0, p1, a[9]);  a[10] = fma(wq0, p2, a[10]);
-  a[11] = fma(wq1, p0, a[11]); a[12] = fma(wq1, p1, a[12]); a[13] = fma(wq1, p2, a[13]);
-  a[14] = fma(wq2, p0, a[14]); a[15] = fma(wq2, p1, a[15]); a[16] = fma(wq2, p2, a[16]);
-  a[17] += valid ? 1.0 : 0.0;
-  a[18] += (in && !fin) ? 1.0 : 0.0;
-}
-
 // Residual r = s R p + t - q and centred model point y_c = s R p + t - c,
 // formed in FP64 (so that r keeps full FP32 relative precision however far
 // the points are from the origin), then rounded to FP32.
@@ -163,47 +142,8 @@ __device__ inline void residual(const PointParams& P, const float* x, float (&r)
   }
 }
 
-// One Gauss-Newton point (IRLS weight recomputed at the current iterate).
-// Accumulated in FP32 over the few points a lane handles per tile; the
-// butterfly and everything above it are pairwise, FP64 from the workgroup up.
-__device__ inline void point_gn(float (&a)[NSTAT], const PointParams& P, float* x, bool in, float tau,
-                                float delta) {
-  const bool valid = in && finite7(x) && x[6] >= tau;
-  if (!valid) {
-#pragma unroll
-    for (int j = 0; j < 7; ++j) x[j] = 0.0f;
-  }
-  float r[3], y[3];
-  residual(P, x, r, y);
-  const float e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-  const bool inl = e2 <= delta * delta;
-  float psi, rho;
-  if (inl) {
-    psi = 1.0f;
-    rho = 0.5f * e2;
-  } else {
-    const float ie = rsqrtf(e2);
-    psi = delta * ie;
-    rho = delta * (e2 * ie - 0.5f * delta);
-  }
-  const float w = x[6];  // zero when invalid
-  const float om = w * psi;
-  const float oy0 = om * y[0], oy1 = om * y[1], oy2 = om * y[2];
-  a[0] += om;
-  a[1] += oy0; a[2] += oy1; a[3] += oy2;
-  a[4] = fmaf(oy0, y[0], a[4]); a[5] = fmaf(oy0, y[1], a[5]); a[6] = fmaf(oy0, y[2], a[6]);
-  a[7] = fmaf(oy1, y[1], a[7]); a[8] = fmaf(oy1, y[2], a[8]); a[9] = fmaf(oy2, y[2], a[9]);
-  a[10] = fmaf(om, r[0], a[10]); a[11] = fmaf(om, r[1], a[11]); a[12] = fmaf(om, r[2], a[12]);
-  a[13] += oy1 * r[2] - oy2 * r[1];
-  a[14] += oy2 * r[0] - oy0 * r[2];
-  a[15] += oy0 * r[1] - oy1 * r[0];
-  a[16] = fmaf(oy0, r[0], fmaf(oy1, r[1], fmaf(oy2, r[2], a[16])));
-  a[17] = fmaf(w, rho, a[17]);
-  a[18] += (valid && inl) ? 1.0f : 0.0f;
-}
-
 // Cost at S: 0 sum w, 1 sum w rho, 2 V (FP64 per lane).
-__device__ inline void point_cost(double (&a)[NSTAT], const PointParams& P, float* x, bool in, float tau,
+__device__ inline void point_cost(double (&a)[3], const PointParams& P, float* x, bool in, float tau,
                                   float delta) {
   const bool valid = in && finite7(x) && x[6] >= tau;
   if (!valid) {
@@ -279,19 +219,54 @@ __device__ inline void block_store_f32(float (&acc)[NSTAT], double (*red)[NSTAT]
   __syncthreads();
 }
 
-// Reduce NSTAT per-lane values over the workgroup and store one FP64 partial.
-template <typename T, int WG>
-__device__ inline void block_store(T (&acc)[NSTAT], double (*red)[NSTAT], double* out, int nstat) {
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+// One DPP step on a double: both 32-bit halves move with the same control.
+template <int CTRL, int ROWS>
+__device__ inline double dpp_f64(double x) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROWS, 0xf, false);
+  const unsigned hi = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROWS, 0xf, false);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// FP64 sums over the 64 lanes of a wavefront: the same fixed DPP tree as the
+// FP32 reduction above, advanced step-major over the N sums; every lane ends
+// with the totals (read from lane 63).
+template <int N>
+__device__ inline void wave_totals_f64(double (&v)[N]) {
 #pragma unroll
-  for (int j = 0; j < NSTAT; ++j) {
-    if (j < nstat) {
-      const T v = wave_sum(acc[j]);
-      if (lane == 0) red[wv][j] = (double)v;
-    }
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0xb1, 0xf>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0x4e, 0xf>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0x141, 0xf>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0x140, 0xf>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0x142, 0xa>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) v[j] += dpp_f64<0x143, 0xc>(v[j]);
+#pragma unroll
+  for (int j = 0; j < N; ++j) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v[j]);
+    const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, 63);
+    const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), 63);
+    v[j] = __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+  }
+}
+
+// Reduce N <= NSTAT per-lane FP64 values over the workgroup (DPP within a
+// wavefront, then across wavefronts through LDS) and store N FP64 sums.
+template <int WG, int N>
+__device__ inline void block_store_f64(double (&acc)[N], double (*red)[NSTAT], double* out) {
+  static_assert(N <= NSTAT, "too many sums");
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  wave_totals_f64(acc);
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < N; ++j) red[wv][j] = acc[j];
   }
   __syncthreads();
-  if ((int)threadIdx.x < nstat) {
+  if ((int)threadIdx.x < N) {
     double s = 0.0;
 #pragma unroll
     for (int q = 0; q < WG / 64; ++q) s += red[q][threadIdx.x];
@@ -382,46 +357,97 @@ __device__ inline void tile_gn(const Shape& sh, const void* const* pl, const Til
   block_store_f32<WG>(a, red, out);
 }
 
+// Moments pass over one tile: FP64 products and per-lane FP64 sums (the
+// coordinates are uncentred here, so the second moments must keep more than
+// FP32 precision), integer counts, DPP wavefront reduction.
+template <int DT, int WG, int ITEMS>
+__device__ inline void tile_moments(const Shape& sh, const void* const* pl, const TileDesc& td,
+                                   double (*red)[NSTAT], double* out) {
+  constexpr int VEC = Planes<DT>::VEC;
+  double a[NSTAT];
+#pragma unroll
+  for (int j = 0; j < NSTAT; ++j) a[j] = 0.0;
+  int nvalid = 0, nbad = 0;
+  const float tau = sh.tau;
+  const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+#pragma unroll 1
+  for (int it = 0; it < ITEMS; ++it) {
+    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+    if (rel0 >= end_rel) break;
+    float v[7][VEC];
+    Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
+      float x[7];
+#pragma unroll
+      for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+      const bool fin = finite7(x);
+      const bool valid = in && fin && x[6] >= tau;
+      nvalid += valid ? 1 : 0;
+      nbad += (in && !fin) ? 1 : 0;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;
+      const double w = x[6];
+      const double p0 = x[0], p1 = x[1], p2 = x[2], q0 = x[3], q1 = x[4], q2 = x[5];
+      const double wp0 = w * p0, wp1 = w * p1, wp2 = w * p2;
+      const double wq0 = w * q0, wq1 = w * q1, wq2 = w * q2;
+      a[0] += w;
+      a[1] += wp0; a[2] += wp1; a[3] += wp2;
+      a[4] += wq0; a[5] += wq1; a[6] += wq2;
+      a[7] = fma(wp0, p0, fma(wp1, p1, fma(wp2, p2, a[7])));
+      a[8] = fma(wq0, p0, a[8]);  a[9] = fma(wq0, p1, a[9]);  a[10] = fma(wq0, p2, a[10]);
+      a[11] = fma(wq1, p0, a[11]); a[12] = fma(wq1, p1, a[12]); a[13] = fma(wq1, p2, a[13]);
+      a[14] = fma(wq2, p0, a[14]); a[15] = fma(wq2, p1, a[15]); a[16] = fma(wq2, p2, a[16]);
+    }
+  }
+  a[17] = (double)nvalid;
+  a[18] = (double)nbad;
+  block_store_f64<WG, NSTAT>(a, red, out);
+}
+
+// Cost pass over one tile: sum w, sum w rho (FP64 residuals, FP64 sums), V.
+template <int DT, int WG, int ITEMS>
+__device__ inline void tile_cost(const Shape& sh, const void* const* pl, const TileDesc& td, const PointParams& P,
+                                 double (*red)[NSTAT], double* out) {
+  constexpr int VEC = Planes<DT>::VEC;
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (P.active) {
+    const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+#pragma unroll 1
+    for (int it = 0; it < ITEMS; ++it) {
+      const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+      if (rel0 >= end_rel) break;
+      float v[7][VEC];
+      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
+        float x[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+        point_cost(acc, P, x, in, sh.tau, sh.delta_f);
+      }
+    }
+  }
+  block_store_f64<WG, 3>(acc, red, out);
+}
+
 template <int DT, int MODE, int WG, int ITEMS>
 __device__ inline void tile_body(const Shape& sh, const void* const* pl, const TileDesc& td,
                                  const PointParams& P, double (*red)[NSTAT], double* out) {
   if constexpr (MODE == MODE_GN) {
     tile_gn<DT, WG, ITEMS>(sh, pl, td, P, red, out);
-    return;
+  } else if constexpr (MODE == MODE_MOMENTS) {
+    tile_moments<DT, WG, ITEMS>(sh, pl, td, red, out);
+  } else {
+    static_assert(MODE == MODE_COST, "unknown pass mode");
+    tile_cost<DT, WG, ITEMS>(sh, pl, td, P, red, out);
   }
-  constexpr int VEC = Planes<DT>::VEC;
-  using Acc = typename std::conditional<MODE == MODE_GN, float, double>::type;
-  Acc acc[NSTAT];
-#pragma unroll
-  for (int j = 0; j < NSTAT; ++j) acc[j] = Acc(0);
-  const bool run = (MODE == MODE_MOMENTS) || P.active;
-  if (run) {
-#pragma unroll 1
-    for (int it = 0; it < ITEMS; ++it) {
-      const int64_t g0 = td.begin + (int64_t)(it * WG + (int)threadIdx.x) * VEC;
-      if (g0 < td.end) {
-        float v[7][VEC];
-        Planes<DT>::load(pl, g0, sh.n_points, v);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const int64_t g = g0 + e;
-          const bool in = (g >= td.lo) && (g < td.end);
-          float x[7];
-#pragma unroll
-          for (int j = 0; j < 7; ++j) x[j] = v[j][e];
-          if constexpr (MODE == MODE_MOMENTS) point_moments(acc, x, in, sh.tau);
-          else if constexpr (MODE == MODE_GN) point_gn(acc, P, x, in, sh.tau, sh.delta_f);
-          else point_cost(acc, P, x, in, sh.tau, sh.delta_f);
-        }
-      }
-    }
-  }
-  const int nstat = (MODE == MODE_COST) ? 3 : NSTAT;
-  block_store<Acc, WG>(acc, red, out, nstat);
 }
 
-// Sum the pair's tile partials in a fixed order (lane-strided, then a fixed
-// butterfly): the same value on every run.
+// Sum the pair's tile partials in a fixed order (lane-strided, then the fixed
+// DPP tree): the same value on every run, in every lane.
 __device__ inline void pair_sums(const Work& w, const PairSched& sc, int nstat, double (&s)[NSTAT]) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
@@ -432,8 +458,7 @@ __device__ inline void pair_sums(const Work& w, const PairSched& sc, int nstat, 
     for (int j = 0; j < NSTAT; ++j)
       if (j < nstat) s[j] += p[j];
   }
-#pragma unroll
-  for (int j = 0; j < NSTAT; ++j) s[j] = wave_sum(s[j]);
+  wave_totals_f64(s);
 }
 
 }  // namespace s3a

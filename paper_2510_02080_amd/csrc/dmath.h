@@ -275,16 +275,18 @@ S3A_HD double int_exp_pow(int n, double sg) {
 }
 
 // Coefficients of the double series used for small steps (th = |omega| < 0.1,
-// |sigma| < 0.1), all from int_0^1 e^{sigma u} f(u th) du expanded in sigma
+// |sigma| < 1), all from int_0^1 e^{sigma u} f(u th) du expanded in sigma
 // and th^2:
 //   A  = sin th / th            = sum_m (-1)^m th^{2m} / (2m+1)!
 //   B  = (1 - cos th) / th^2    = sum_m (-1)^m th^{2m} / (2m+2)!
 //   c1 = int e^{su} sin(u th)/th        = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+1)! k! (2m+k+2))
 //   c2 = int e^{su} (1-cos(u th))/th^2  = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+2)! k! (2m+k+3))
 //   a0 = int e^{su}                     = sum_k s^k / (k+1)!
-// Truncation at m < 5, k < 12 leaves terms below 1e-20.
+// Truncation at m < 5, k < 20 leaves terms below 1e-19 of the leading one
+// (0.1^10 / 11! and 1 / 20!).
+constexpr int kSeriesM = 5, kSeriesK = 20;
 struct SmallStepSeries {
-  double c1[5][12], c2[5][12], a0[12], A[5], B[5];
+  double c1[kSeriesM][kSeriesK], c2[kSeriesM][kSeriesK], a0[kSeriesK], A[kSeriesM], B[kSeriesM];
 };
 
 constexpr SmallStepSeries make_small_step_series() {
@@ -292,21 +294,21 @@ constexpr SmallStepSeries make_small_step_series() {
   double fact[40] = {};
   fact[0] = 1.0;
   for (int i = 1; i < 40; ++i) fact[i] = fact[i - 1] * i;
-  for (int m = 0; m < 5; ++m) {
+  for (int m = 0; m < kSeriesM; ++m) {
     const double sg = (m & 1) ? -1.0 : 1.0;
     t.A[m] = sg / fact[2 * m + 1];
     t.B[m] = sg / fact[2 * m + 2];
-    for (int k = 0; k < 12; ++k) {
+    for (int k = 0; k < kSeriesK; ++k) {
       t.c1[m][k] = sg / (fact[2 * m + 1] * fact[k] * (2 * m + k + 2));
       t.c2[m][k] = sg / (fact[2 * m + 2] * fact[k] * (2 * m + k + 3));
     }
   }
-  for (int k = 0; k < 12; ++k) t.a0[k] = 1.0 / fact[k + 1];
+  for (int k = 0; k < kSeriesK; ++k) t.a0[k] = 1.0 / fact[k + 1];
   return t;
 }
 
 // The table lives in read-only memory and is walked by loops that are not
-// unrolled, so its 142 coefficients are loaded as needed instead of being
+// unrolled, so its 230 coefficients are loaded as needed instead of being
 // materialised in registers.
 #if defined(__HIPCC__) || defined(__HIP__)
 __device__ __constant__ constexpr SmallStepSeries kSmallStep = make_small_step_series();
@@ -323,16 +325,16 @@ S3A_HD void sim3_RV(const double* w, double sg, double* R, double* V) {
   const double th = sqrt(th2);
   double A, B;  // Rodrigues coefficients sin(th)/th, (1 - cos th)/th^2
   double c1, c2, a0;
-  if (th < 0.1 && fabs(sg) < 0.1) {
+  if (th < 0.1 && fabs(sg) < 1.0) {
     const SmallStepSeries& T = kSmallStep;
     A = 0.0; B = 0.0; c1 = 0.0; c2 = 0.0; a0 = 0.0;
     S3A_NO_UNROLL
-    for (int k = 11; k >= 0; --k) a0 = a0 * sg + T.a0[k];
+    for (int k = kSeriesK - 1; k >= 0; --k) a0 = a0 * sg + T.a0[k];
     S3A_NO_UNROLL
-    for (int mm = 4; mm >= 0; --mm) {
+    for (int mm = kSeriesM - 1; mm >= 0; --mm) {
       double p1 = 0.0, p2 = 0.0;
       S3A_NO_UNROLL
-      for (int k = 11; k >= 0; --k) {
+      for (int k = kSeriesK - 1; k >= 0; --k) {
         p1 = p1 * sg + T.c1[mm][k];
         p2 = p2 * sg + T.c2[mm][k];
       }

@@ -138,7 +138,7 @@ __device__ inline void finalize_gn(const Shape& sh, const CallDesc* cd, Work& w,
   const double nan = __builtin_nan("");
   const double c[3] = {st->cq[0], st->cq[1], st->cq[2]};
   const double C = st->C;
-  st->cost_lin = s[17] / C;
+  st->cost_lin = s[17] / C;  // the cost and inlier count at the linearisation point
   st->inl_lin = (int64_t)s[18];
   double Hp[28], g[7], x[7];
   assemble_gn_packed(s, Hp, g);
@@ -157,7 +157,9 @@ __device__ inline void finalize_gn(const Shape& sh, const CallDesc* cd, Work& w,
     } else {
       st->S = Snew;
       st->iters = pass;
-      // uncentred statistics: y = y_c + c
+    }
+    if (status == S3A_PAIR_OK && pass == sh.K) {
+      // Reported with the last step only: uncentred statistics, y = y_c + c
       double u[17];
       const double A0 = s[0], a[3] = {s[1], s[2], s[3]}, br[3] = {s[10], s[11], s[12]};
       u[0] = A0;
@@ -175,10 +177,11 @@ __device__ inline void finalize_gn(const Shape& sh, const CallDesc* cd, Work& w,
       u[16] = s[16] + c[0] * br[0] + c[1] * br[1] + c[2] * br[2];
       assemble_gn_packed(u, Hp, g);
       // packed lower -> row-major upper triangle (same values, H symmetric)
+      const double invC = 1.0 / C;
       int m = 0;
       for (int i = 0; i < 7; ++i)
-        for (int j = i; j < 7; ++j) st->H[m++] = Hp[j * (j + 1) / 2 + i] / C;
-      for (int i = 0; i < 7; ++i) st->g[i] = g[i] / C;
+        for (int j = i; j < 7; ++j) st->H[m++] = Hp[j * (j + 1) / 2 + i] * invC;
+      for (int i = 0; i < 7; ++i) st->g[i] = g[i] * invC;
     }
   } else {
     status = S3A_PAIR_DEGENERATE;
