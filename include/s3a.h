@@ -216,7 +216,8 @@ int s3a_pose_graph_solve(s3a_handle* h, int32_t n_nodes, int32_t n_edges, const 
 typedef struct {
   int32_t wg;       /* workgroup size: 256 or 512 */
   int32_t items;    /* vector loads per thread per tile: 2, 4, 8, or 16 (with wg 256) */
-  int32_t occupancy;/* persistent workgroups per compute unit: 1..8 */
+  int32_t occupancy;/* workgroups per compute unit looping over the tiles: 1..8; 0 = one workgroup
+                       per tile (not for the persistent launch, which then uses 4) */
   int32_t window;   /* pairs per scheduling window in the persistent launch (0 = all) */
 } s3a_tuning;
 

@@ -205,7 +205,7 @@ LaunchCfg pick_cfg(s3a_handle* h, int dtype, int64_t n_points) {
 
 bool valid_cfg(const LaunchCfg& c) {
   return (c.wg == 256 || c.wg == 512) && (c.items == 2 || c.items == 4 || c.items == 8 || (c.items == 16 && c.wg == 256)) &&
-         c.occupancy >= 1 &&
+         c.occupancy >= 0 &&
          c.occupancy <= 8 && c.window >= 0;
 }
 
@@ -236,8 +236,11 @@ CallDesc make_call(const s3a_align_desc* d) {
 // stream just before the kernels that read it.
 CallDesc* desc_slot(s3a_handle* h) { return h->desc; }
 
+// Occupancy 0: one workgroup per tile (the hardware balances the tail);
+// otherwise a fixed number of workgroups per compute unit loops over the tiles.
 int grid_for(s3a_handle* h, const LaunchCfg& lc, int64_t tiles) {
-  const int64_t g = std::min<int64_t>(tiles, (int64_t)lc.occupancy * h->n_cu * (256 / std::min(lc.wg, 256)));
+  const int64_t g = lc.occupancy == 0 ? tiles
+                                      : std::min<int64_t>(tiles, (int64_t)lc.occupancy * h->n_cu * (256 / std::min(lc.wg, 256)));
   return (int)std::max<int64_t>(g, 1);
 }
 
@@ -275,7 +278,7 @@ hipError_t enqueue_batched(s3a_handle* h, int dtype, const LaunchCfg& lc, const 
   if (e != hipSuccess) return e;
   e = launch_init_outputs(sh, dcd, st);
   if (e != hipSuccess) return e;
-  const int grid = lc.occupancy * h->n_cu;
+  const int grid = (lc.occupancy > 0 ? lc.occupancy : 4) * h->n_cu;
   TimedLaunch tl(h, st);
   return launch_persistent(dtype, lc, sh, dcd, h->w, grid, st);
 }
@@ -581,7 +584,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   float best_ms = 1e30f;
   const int wgs[2] = {256, 512};
   const int its[4] = {2, 4, 8, 16};
-  const int occs[3] = {2, 4, 8};
+  const int occs[4] = {0, 2, 4, 8};
   const bool persistent = (d->flags & S3A_FLAG_PERSISTENT) && !(d->flags & S3A_FLAG_PLAIN);
   s3a_align_desc dd = *d;
   dd.flags &= ~S3A_FLAG_PLAIN;
@@ -589,7 +592,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
     for (int it : its)
       for (int oc : occs) {
         if (wg == 512 && (oc > 4 || it > 8)) continue;
-        if (!persistent && oc != 4) continue;
+        if (persistent ? oc == 0 : (oc != 0 && oc != 4)) continue;
         LaunchCfg c;
         c.wg = wg;
         c.items = it;

@@ -14,9 +14,11 @@
 #if defined(__HIPCC__) || defined(__HIP__)
 #define S3A_HD __host__ __device__ inline
 #define S3A_NO_UNROLL _Pragma("unroll 1")
+#define S3A_UNROLL _Pragma("unroll")
 #else
 #define S3A_HD inline
 #define S3A_NO_UNROLL
+#define S3A_UNROLL
 #endif
 
 namespace s3a {
@@ -274,47 +276,12 @@ S3A_HD double int_exp_pow(int n, double sg) {
   return F;
 }
 
-// Coefficients of the double series used for small steps (th = |omega| < 0.1,
-// |sigma| < 1), all from int_0^1 e^{sigma u} f(u th) du expanded in sigma
-// and th^2:
-//   A  = sin th / th            = sum_m (-1)^m th^{2m} / (2m+1)!
-//   B  = (1 - cos th) / th^2    = sum_m (-1)^m th^{2m} / (2m+2)!
-//   c1 = int e^{su} sin(u th)/th        = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+1)! k! (2m+k+2))
-//   c2 = int e^{su} (1-cos(u th))/th^2  = sum_{m,k} (-1)^m th^{2m} s^k / ((2m+2)! k! (2m+k+3))
-//   a0 = int e^{su}                     = sum_k s^k / (k+1)!
-// Truncation at m < 5, k < 20 leaves terms below 1e-19 of the leading one
-// (0.1^10 / 11! and 1 / 20!).
-constexpr int kSeriesM = 5, kSeriesK = 20;
-struct SmallStepSeries {
-  double c1[kSeriesM][kSeriesK], c2[kSeriesM][kSeriesK], a0[kSeriesK], A[kSeriesM], B[kSeriesM];
-};
-
-constexpr SmallStepSeries make_small_step_series() {
-  SmallStepSeries t{};
-  double fact[40] = {};
-  fact[0] = 1.0;
-  for (int i = 1; i < 40; ++i) fact[i] = fact[i - 1] * i;
-  for (int m = 0; m < kSeriesM; ++m) {
-    const double sg = (m & 1) ? -1.0 : 1.0;
-    t.A[m] = sg / fact[2 * m + 1];
-    t.B[m] = sg / fact[2 * m + 2];
-    for (int k = 0; k < kSeriesK; ++k) {
-      t.c1[m][k] = sg / (fact[2 * m + 1] * fact[k] * (2 * m + k + 2));
-      t.c2[m][k] = sg / (fact[2 * m + 2] * fact[k] * (2 * m + k + 3));
-    }
-  }
-  for (int k = 0; k < kSeriesK; ++k) t.a0[k] = 1.0 / fact[k + 1];
-  return t;
+// 1 / n! for the series below (folded to constants where the loops unroll).
+constexpr double inv_factorial(int n) {
+  double f = 1.0;
+  for (int i = 2; i <= n; ++i) f *= i;
+  return 1.0 / f;
 }
-
-// The table lives in read-only memory and is walked by loops that are not
-// unrolled, so its 230 coefficients are loaded as needed instead of being
-// materialised in registers.
-#if defined(__HIPCC__) || defined(__HIP__)
-__device__ __constant__ constexpr SmallStepSeries kSmallStep = make_small_step_series();
-#else
-constexpr SmallStepSeries kSmallStep = make_small_step_series();
-#endif
 
 // Rotation R = exp([omega]_x) (Rodrigues) and the translation map
 // V = int_0^1 e^{sigma u} exp(u [omega]_x) du = a0 I + c1 [omega]_x + c2 [omega]_x^2,
@@ -325,23 +292,35 @@ S3A_HD void sim3_RV(const double* w, double sg, double* R, double* V) {
   const double th = sqrt(th2);
   double A, B;  // Rodrigues coefficients sin(th)/th, (1 - cos th)/th^2
   double c1, c2, a0;
-  if (th < 0.1 && fabs(sg) < 1.0) {
-    const SmallStepSeries& T = kSmallStep;
-    A = 0.0; B = 0.0; c1 = 0.0; c2 = 0.0; a0 = 0.0;
-    S3A_NO_UNROLL
-    for (int k = kSeriesK - 1; k >= 0; --k) a0 = a0 * sg + T.a0[k];
-    S3A_NO_UNROLL
-    for (int mm = kSeriesM - 1; mm >= 0; --mm) {
-      double p1 = 0.0, p2 = 0.0;
-      S3A_NO_UNROLL
-      for (int k = kSeriesK - 1; k >= 0; --k) {
-        p1 = p1 * sg + T.c1[mm][k];
-        p2 = p2 * sg + T.c2[mm][k];
+  if (th < 0.1 && fabs(sg) < 4.0) {
+    // Expansion in th^2 with F_n(sigma) = int_0^1 e^{sigma u} u^n du:
+    //   c1 = sum_m (-1)^m th^{2m} F_{2m+1} / (2m+1)!,  c2 = sum_m (-1)^m th^{2m} F_{2m+2} / (2m+2)!,
+    //   a0 = F_0, and A, B the Taylor series of sin th / th and (1 - cos th) / th^2,
+    // truncated after m = 4 (th^10 / 11! < 3e-18). The F_n come from the downward
+    // recurrence n F_{n-1} = e^sigma - sigma F_n started at n = 40 from
+    // F_40 ~ e^sigma / (41 + sigma): each step scales the start error by |sigma| / n,
+    // so below n = 10 it is under 1e-23 for |sigma| < 4. Horner in th^2 runs
+    // with the recurrence (m falls as n falls).
+    const double es = exp(sg);
+    double F = es / (41.0 + sg);
+    c1 = 0.0; c2 = 0.0;
+    S3A_UNROLL
+    for (int n = 40; n >= 1; --n) {
+      F = (es - sg * F) * (1.0 / n);  // F_{n-1}
+      const int j = n - 1;
+      if (j >= 1 && j <= 10) {
+        const double coef = (((j - 1) / 2) & 1 ? -1.0 : 1.0) * inv_factorial(j);
+        if (j & 1) c1 = c1 * th2 + coef * F;
+        else c2 = c2 * th2 + coef * F;
       }
-      c1 = c1 * th2 + p1;
-      c2 = c2 * th2 + p2;
-      A = A * th2 + T.A[mm];
-      B = B * th2 + T.B[mm];
+    }
+    a0 = F;
+    A = 0.0; B = 0.0;
+    S3A_UNROLL
+    for (int m = 4; m >= 0; --m) {
+      const double sgn = (m & 1) ? -1.0 : 1.0;
+      A = A * th2 + sgn * inv_factorial(2 * m + 1);
+      B = B * th2 + sgn * inv_factorial(2 * m + 2);
     }
   } else if (th < 0.1) {
     a0 = int_exp_pow(0, sg);

@@ -131,7 +131,7 @@ def test_back_to_back_calls_different_inputs(h):
             check_pair(T[k], info[k], irls.irls_align(p, q, c, b.tau, b.delta, b.iters), where=f"pair {k}")
 
 
-@pytest.mark.parametrize("cfg", [(256, 2, 2), (256, 8, 4), (512, 4, 2), (512, 8, 1)])
+@pytest.mark.parametrize("cfg", [(256, 2, 2), (256, 8, 4), (512, 4, 2), (512, 8, 1), (512, 4, 0), (256, 16, 0)])
 def test_launch_shapes_agree(h, cfg):
     b = ragged_batch([100000, 33333, 4097], seed=8)
     h.set_tuning(s3a.F32, wg=cfg[0], items=cfg[1], occupancy=cfg[2])
@@ -142,3 +142,18 @@ def test_launch_shapes_agree(h, cfg):
     for k in range(b.n_pairs):
         p, q, c = b.decoded_pair(k)
         check_pair(T[k], info[k], irls.irls_align(p, q, c, b.tau, b.delta, b.iters), where=f"cfg {cfg} pair {k}")
+
+
+def test_grid_size_does_not_change_bits(h):
+    """Per-tile partials do not depend on how many workgroups sweep the tiles:
+    one workgroup per tile and 4 per compute unit give identical results."""
+    b = ragged_batch([100000, 33333, 4097, 0, 250000], seed=9)
+    out = []
+    for occ in (0, 4):
+        h.set_tuning(s3a.F32, wg=512, items=4, occupancy=occ)
+        try:
+            out.append(run(h, b))
+        finally:
+            h.set_tuning(s3a.F32)
+    assert np.array_equal(np.asarray(out[0][0]), np.asarray(out[1][0]))
+    assert out[0][1].tobytes() == out[1][1].tobytes()

@@ -59,10 +59,11 @@ def c_log(lib, T):
 def test_exp_matches_oracle(lib):
     rng = np.random.default_rng(1)
     cases = [rand_xi(rng) for _ in range(200)]
-    # small-angle, small-scale and mixed branches
+    # small-angle series (|sigma| < 4), its large-sigma fallback, and the closed form
     cases += [np.array([0.3, -0.1, 0.2, a, -0.5 * a, 0.2 * a, sg])
               for a in (0.0, 1e-9, 1e-5, 0.05, 0.0999 / 1.14, 0.1001 / 1.14, 0.5)
-              for sg in (0.0, 1e-8, -3e-4, 0.0999, -0.0999, 0.1001, -0.1001, 0.7, 2.5, -3.1)]
+              for sg in (0.0, 1e-8, -3e-4, 0.0999, -0.0999, 0.1001, -0.1001, 0.7, 2.5, -3.1,
+                         3.999, -3.999, 4.001, -4.001, 6.5, -7.0)]
     for xi in cases:
         assert np.abs(c_exp(lib, xi) - sim3.exp(xi)).max() < 1e-12 * max(1.0, np.abs(sim3.exp(xi)).max())
 
