@@ -1,6 +1,6 @@
 """FP64 CPU oracle for dense Sim(3) alignment, its cost adjoint and the Sim(3)
-pose-graph solve (EC3R-SLAM mapping back end: Sec. III-C.2 eq. (sim3) and
-Sec. III-E).
+pose-graph solve, and point correction (EC3R-SLAM mapping back end:
+Sec. III-C.2 eq. (sim3), Sec. III-C.3 and Sec. III-E).
 
 TEST INFRASTRUCTURE ONLY. This package is the plain, slow, obviously correct
 reference that the HIP path is checked against. Only ``tests/``,
@@ -16,5 +16,7 @@ irls     : confidence mask/weights + Umeyama start + Huber IRLS Gauss-Newton
 cost     : Huber-weighted alignment cost, its analytic gradient, and central
            finite differences
 pgo      : dense Gauss-Newton Sim(3) pose-graph solve (Sec. III-E)
+points   : point correction: submap points to the world frame, sparse-map
+           replacement (Sec. III-C.3)
 metrics  : pose-error measures used to compare two Sim(3) estimates
 """
