@@ -34,6 +34,7 @@ HBM_PEAK_GBS = 8000.0
 FP32_B_PER_PT = 28   # px py pz qx qy qz c, 4 B each
 BF16_B_PER_PT = 14
 ADJ_B_PER_PT = 28 + 28  # FP32 planes in, FP32 gradients out
+POINTS_B_PER_PT = 12 + 12  # FP32 xyz in, FP32 world xyz out
 TOL = (1e-5, 1e-5, 1e-5)
 
 # HBM traffic of the roofline kernel (k_pass, FP32, 256-pair batch) per pass
@@ -92,7 +93,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="fewer pairs verified, no plain/config-1 leg")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="bf16,plain,adjoint,pgo", help="comma list of extra legs")
+    ap.add_argument("--legs", default="bf16,plain,adjoint,pgo,points", help="comma list of extra legs")
     ap.add_argument("--verify", default="all", choices=["all", "sample", "none"])
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--tuning", default="", help="force the launch shape wg,items,occupancy (skips autotuning)")
@@ -250,6 +251,34 @@ def main():
                                           batched_speedup=value / (V1 / (ms1 / 1e3)))
             log(f"plain fp32 cfg1: {ms1:.2f} ms/step, {V1 / (ms1 / 1e3) / 1e9:.3f} Gpts/s; verify {ver1}")
             del pm1
+
+    # ---- point correction: the batch's source points to the world frame, then a sparse-map replacement
+    if "points" in legs:
+        Np = (b2.n_points + 3) // 4 * 4
+        xt = torch.zeros((3, Np), dtype=torch.float32)
+        for j, nm in enumerate(("px", "py", "pz")):
+            xt[j, :b2.n_points] = torch.from_numpy(b2.planes[nm])
+        xt = xt.to(dev)[:, :b2.n_points]
+        off2 = torch.from_numpy(b2.offsets).to(dev)
+        rng = np.random.default_rng(5)
+        Tw = torch.from_numpy(np.tile(np.r_[np.eye(3).ravel(), 0.5, -0.25, 2.0, 1.25, 0, 0, 0], (b2.n_pairs, 1))).to(dev)
+        wout = torch.empty((3, Np), dtype=torch.float32, device=dev)[:, :b2.n_points]
+        xf = lambda: h.transform_points(xt, off2, Tw, out=wout)
+        ms_t = timed(xf, args.steps, args.warmup)
+        kt, _ = kernel_ms(xf, args.steps)
+        n_corr = 1 << 20
+        src = torch.from_numpy(rng.integers(0, b2.n_points, n_corr)).to(dev)
+        dst = torch.from_numpy(rng.permutation(4 * n_corr)[:n_corr]).to(dev)
+        sparse = torch.zeros((3, 4 * n_corr), dtype=torch.float32, device=dev)
+        cf = lambda: h.correct_points(wout, src, dst, sparse)
+        ms_c = timed(cf, args.steps, args.warmup)
+        res["points_fp32"] = dict(transform_ms=ms_t, transform_kernel_ms=kt, points=b2.n_points,
+                                  transform_gbs=POINTS_B_PER_PT * b2.n_points / (kt / 1e3) / 1e9,
+                                  transform_frac=POINTS_B_PER_PT * b2.n_points / (kt / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  correct_ms=ms_c, corrections=n_corr)
+        log(f"points: transform {ms_t:.3f} ms (kernel {kt:.3f}, {res['points_fp32']['transform_gbs']:.0f} GB/s), "
+            f"correct {n_corr} in {ms_c:.3f} ms")
+        del xt, wout, sparse
 
     # ---- cost forward + adjoint (differentiation workload)
     if "adjoint" in legs:

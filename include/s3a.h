@@ -221,6 +221,40 @@ typedef struct {
   int32_t window;   /* pairs per scheduling window in the persistent launch (0 = all) */
 } s3a_tuning;
 
+/*
+ * Point correction (Sec. III-C.3), step 1: submap points to the world frame.
+ * Submap k owns rows offsets[k] .. offsets[k+1]-1 of three coordinate planes
+ * (x, y, z; FP32 or BF16 per dtype), and each of its rows maps to
+ * s_k R_k x + t_k, formed in FP64 and rounded once to FP32, in the three FP32
+ * output planes. Rows outside every submap are copied through as FP32.
+ *   offsets:  device, n_submaps + 1 int64, non-decreasing, offsets[0] >= 0,
+ *             offsets[n_submaps] <= n_points. Otherwise nothing is
+ *             transformed, every output is NaN and *status = 1.
+ *   T:        device, n_submaps similarities.
+ *   x, y, z:  device planes of n_points, 16-byte aligned; out_*: device FP32
+ *             planes of n_points, 16-byte aligned. With dtype F32 the outputs
+ *             may be the input planes (in place).
+ *   status:   device int32, or NULL: 0, or 1 for invalid offsets.
+ * Bad arguments (null planes, misalignment, negative sizes) return S3A_EINVAL.
+ */
+int s3a_transform_points(s3a_handle* h, int32_t dtype, int64_t n_points, int32_t n_submaps, const int64_t* offsets,
+                         const s3a_sim3* T, const void* x, const void* y, const void* z, float* out_x, float* out_y,
+                         float* out_z, int32_t* status, s3a_stream stream);
+
+/*
+ * Point correction, step 2: points of the tracker's sparse map that have a
+ * dense counterpart take its world coordinates:
+ *   sparse[dst[m]] = world[src[m]]   for m < n_corr with 0 <= src[m] < n_world
+ *                                    and 0 <= dst[m] < n_sparse,
+ * on all three FP32 planes (device). Other m are skipped and counted: the
+ * count is added to *n_skipped (device, may be NULL). src, dst: device int64.
+ * Destinations should be distinct; for a repeated one, which write survives
+ * is unspecified.
+ */
+int s3a_correct_points(s3a_handle* h, int64_t n_corr, const int64_t* src, const int64_t* dst, int64_t n_world,
+                       const float* wx, const float* wy, const float* wz, int64_t n_sparse, float* sx, float* sy,
+                       float* sz, unsigned long long* n_skipped, s3a_stream stream);
+
 /* Time candidate launch shapes on this batch and keep the fastest for its
  * (dtype, size class). Synchronises the stream. best may be NULL. */
 int s3a_autotune(s3a_handle* h, const s3a_align_desc* desc, s3a_tuning* best, s3a_stream stream);

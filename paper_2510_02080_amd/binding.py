@@ -64,6 +64,11 @@ _EXPORTS = {
     "s3a_get_tuning": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Tuning)]),
     "s3a_set_timing": (ctypes.c_int, [c_void_p, ctypes.c_int]),
     "s3a_kernel_time": (ctypes.c_int, [c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32)]),
+    "s3a_transform_points": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, c_void_p,
+                                            c_void_p] + [c_void_p] * 6 + [c_void_p, c_void_p]),
+    "s3a_correct_points": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, ctypes.c_int64, c_void_p,
+                                          c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -113,11 +118,15 @@ class Pointmaps:
     """Seven device planes (FP32, or BF16 bit patterns in int16/uint16 or
     torch.bfloat16 tensors) plus int64 offsets[n_pairs + 1]."""
 
-    def __init__(self, planes, offsets, dtype):
+    def __init__(self, planes, offsets, dtype, covers_all=False):
+        """covers_all: the caller asserts that the offsets are non-decreasing
+        from 0 to N (every stored point belongs to a pair), so gradient
+        buffers need no zeroing outside the pairs."""
         assert len(planes) == 7
         self.planes = list(planes)
         self.offsets = offsets
         self.dtype = dtype
+        self.covers_all = bool(covers_all)
         self.n_points = int(planes[0].numel())
         self.n_pairs = int(offsets.numel()) - 1
         self.device = planes[0].device
@@ -135,7 +144,9 @@ class Pointmaps:
         else:
             planes = [torch.from_numpy(batch.planes[n]).to(device) for n in names]
             dt = F32
-        return Pointmaps(planes, torch.from_numpy(batch.offsets).to(device), dt)
+        off = np.asarray(batch.offsets)
+        covers = len(off) > 1 and off[0] == 0 and off[-1] == planes[0].numel() and bool(np.all(np.diff(off) >= 0))
+        return Pointmaps(planes, torch.from_numpy(off).to(device), dt, covers_all=covers)
 
     def desc(self, tau, delta, iters, flags=0):
         d = AlignDesc()
@@ -197,9 +208,11 @@ class Handle:
         N = pm.n_points
         Np = (N + 3) // 4 * 4  # row stride keeping every plane 16-byte aligned
         dev = pm.device
-        gp = torch.zeros((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[0] else None
-        gq = torch.zeros((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[1] else None
-        gc = torch.zeros(N, dtype=torch.float32, device=dev) if need[2] else None
+        # the library writes every entry inside the pairs; the rest is zeroed here
+        alloc = torch.empty if pm.covers_all else torch.zeros
+        gp = alloc((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[0] else None
+        gq = alloc((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[1] else None
+        gc = alloc(N, dtype=torch.float32, device=dev) if need[2] else None
         gxi = torch.empty((pm.n_pairs, 7), dtype=torch.float64, device=dev) if need[3] else None
         d = pm.desc(tau, delta, 0)
         gps = [_ptr(gp[i]) if gp is not None else None for i in range(3)]
@@ -231,6 +244,36 @@ class Handle:
                                              _ptr(omega), _ptr(T), ctypes.byref(p), ctypes.byref(rep),
                                              _stream(T_meas.device)), self.h)
         return T, rep
+
+    def transform_points(self, xyz, offsets, T, out=None, status=None):
+        """Point correction, step 1. xyz: (3, N) device tensor, FP32 or BF16
+        (torch.bfloat16 or 16-bit integer bit patterns), rows 16-byte aligned;
+        offsets: int64 device (n_submaps + 1); T: (n_submaps, 16) float64
+        device. Returns the (3, N) FP32 world coordinates (out may be xyz for
+        FP32 input: in place)."""
+        dt = F32 if xyz.dtype == torch.float32 else BF16
+        N = int(xyz.shape[1])
+        dev = xyz.device
+        if out is None:
+            Np = (N + 3) // 4 * 4
+            out = torch.empty((3, Np), dtype=torch.float32, device=dev)[:, :N]
+        n_sub = int(offsets.numel()) - 1
+        _check(self.lib.s3a_transform_points(self.h, dt, N, n_sub, _ptr(offsets), _ptr(T), _ptr(xyz[0]), _ptr(xyz[1]),
+                                             _ptr(xyz[2]), _ptr(out[0]), _ptr(out[1]), _ptr(out[2]), _ptr(status),
+                                             _stream(dev)), self.h)
+        return out
+
+    def correct_points(self, world, src, dst, sparse, skipped=None):
+        """Point correction, step 2: sparse[:, dst[m]] = world[:, src[m]] in
+        place ((3, N) and (3, M) FP32 device tensors; src, dst int64 device).
+        skipped: optional int64 device tensor of one element, incremented by
+        the number of out-of-range correspondences."""
+        dev = sparse.device
+        _check(self.lib.s3a_correct_points(self.h, int(src.numel()), _ptr(src), _ptr(dst), int(world.shape[1]),
+                                           _ptr(world[0]), _ptr(world[1]), _ptr(world[2]), int(sparse.shape[1]),
+                                           _ptr(sparse[0]), _ptr(sparse[1]), _ptr(sparse[2]), _ptr(skipped),
+                                           _stream(dev)), self.h)
+        return sparse
 
     def autotune(self, pm, tau, delta=0.05, iters=10, flags=0):
         best = Tuning()

@@ -9,6 +9,7 @@
 
 #include "align_launch.h"
 #include "pgo.h"
+#include "points.h"
 
 using namespace s3a;
 
@@ -57,6 +58,7 @@ struct s3a_handle {
   CallDesc* desc = nullptr;
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
+  int32_t* flags_dev = nullptr;  // small device scratch (offset-check flag of the point transform)
 };
 
 namespace {
@@ -333,6 +335,7 @@ int s3a_destroy(s3a_handle* h) {
   (void)hipDeviceSynchronize();
   clear_graphs(h);
   if (h->ws) (void)hipFree(h->ws);
+  if (h->flags_dev) (void)hipFree(h->flags_dev);
   pgo_free(h->pgo);
   for (auto& ev : h->ev_used) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   for (auto& ev : h->ev_free) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
@@ -640,6 +643,38 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
     best->occupancy = bestc.occupancy;
     best->window = bestc.window;
   }
+  return S3A_OK;
+}
+
+int s3a_transform_points(s3a_handle* h, int32_t dtype, int64_t n_points, int32_t n_submaps, const int64_t* offsets,
+                         const s3a_sim3* T, const void* x, const void* y, const void* z, float* out_x, float* out_y,
+                         float* out_z, int32_t* status, s3a_stream stream) {
+  if (!h || (dtype != S3A_F32 && dtype != S3A_BF16) || n_points < 0 || n_submaps < 0 || !offsets) return S3A_EINVAL;
+  if (n_submaps > 0 && !T) return S3A_EINVAL;
+  if (n_points > 0 && (!x || !y || !z || !out_x || !out_y || !out_z)) return S3A_EINVAL;
+  const void* planes[6] = {x, y, z, out_x, out_y, out_z};
+  for (const void* q : planes)
+    if (((uintptr_t)q & 15) != 0) return S3A_EINVAL;
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  if (!h->flags_dev) S3A_TRY(hipMalloc(&h->flags_dev, 256));
+  S3A_TRY(launch_check_offsets(n_points, n_submaps, offsets, h->flags_dev, status, st));
+  TimedLaunch tl(h, st);
+  S3A_TRY(launch_transform(dtype, n_points, n_submaps, offsets, T, x, y, z, out_x, out_y, out_z, h->flags_dev, st));
+  return S3A_OK;
+}
+
+int s3a_correct_points(s3a_handle* h, int64_t n_corr, const int64_t* src, const int64_t* dst, int64_t n_world,
+                       const float* wx, const float* wy, const float* wz, int64_t n_sparse, float* sx, float* sy,
+                       float* sz, unsigned long long* n_skipped, s3a_stream stream) {
+  if (!h || n_corr < 0 || n_world < 0 || n_sparse < 0) return S3A_EINVAL;
+  if (n_corr > 0 && (!src || !dst)) return S3A_EINVAL;
+  if (n_world > 0 && (!wx || !wy || !wz)) return S3A_EINVAL;
+  if (n_sparse > 0 && (!sx || !sy || !sz)) return S3A_EINVAL;
+  DeviceGuard g(h->device);
+  hipStream_t st = (hipStream_t)stream;
+  TimedLaunch tl(h, st);
+  S3A_TRY(launch_correct(n_corr, src, dst, n_world, wx, wy, wz, n_sparse, sx, sy, sz, n_skipped, st));
   return S3A_OK;
 }
 
