@@ -8,11 +8,13 @@ relative similarity T_ij from registration, with residual
 (zero when T_j = T_i T_ij) and energy chi^2 = sum e_ij^T Omega_ij e_ij. Poses
 start from chaining the relative transforms.
 
-Readings where the section is silent (it names LM in a third-party library and
-leaves Omega unspecified):
+Readings where the section is silent (it names Levenberg-Marquardt in a
+third-party library without its settings, and leaves Omega unspecified):
 * Omega_ij = I_7 unless given.
-* Gauss-Newton, optional Levenberg damping lambda (H + lambda diag(H)); no line
-  search, exactly ``iters`` steps.
+* pgo_solve: Gauss-Newton, optional fixed damping lambda (H + lambda diag(H));
+  no line search, exactly ``iters`` steps.
+* pgo_solve_lm: Levenberg-Marquardt with Marquardt's diagonal scaling and
+  Nielsen's gain-ratio update of lambda (see its docstring).
 * A Huber weight per edge on r = sqrt(e^T Omega e): psi = 1 if r <= delta_pg else
   delta_pg / r (delta_pg = inf turns it off).
 * Gauge: node ``gauge`` held fixed. Left perturbations T <- Exp(xi) T.
@@ -130,3 +132,86 @@ def pgo_solve(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20,
         for a, node in enumerate(free):
             T[node] = sim3.exp(dx[7 * a:7 * a + 7]) @ T[node]
     return dict(T=T, chi2=hist, final_chi2=chi2(T, edges, T_meas, omega), status=status)
+
+
+def huber_energy(r2, huber_delta=np.inf):
+    """F = sum_k rho(r_k), r_k = sqrt(e_k^T Omega e_k), rho(r) = r^2 / 2 up to
+    delta and delta (r - delta / 2) beyond (half of chi^2 without Huber)."""
+    F = 0.0
+    for x in r2:
+        r = np.sqrt(max(float(x), 0.0))
+        F += 0.5 * r * r if r <= huber_delta else huber_delta * (r - 0.5 * huber_delta)
+    return F
+
+
+def edge_r2(T, edges, T_meas, omega=None):
+    out = []
+    for k, (i, j) in enumerate(edges):
+        e = edge_residual(T[int(i)], T[int(j)], T_meas[k])
+        Om = np.eye(7) if omega is None else omega[k]
+        out.append(float(e @ Om @ e))
+    return out
+
+
+def pgo_solve_lm(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20, huber_delta=np.inf,
+                 lam0=1e-4, gauge=0, max_rejects=10):
+    """Levenberg-Marquardt on the pose graph (Sec. III-E names LM). Each trial
+    solves the Gauss-Newton system damped along its own diagonal,
+    (H + lambda diag(H)) dx = -g, over the free nodes, and moves every free node
+    by T <- Exp(dx) T. The trial is kept when it lowers the energy F
+    (huber_energy); the gain ratio rho = (F - F_trial) / pred, with the
+    reduction the quadratic model predicts, pred = dx^T (lambda diag(H) dx - g) / 2,
+    then scales lambda by max(1/3, 1 - (2 rho - 1)^3) and resets nu = 2 (Nielsen's
+    update). A rejected trial (energy not lower, or the damped matrix not
+    positive definite) restores the poses and multiplies lambda by nu, then
+    doubles nu. An iteration ends at its first kept trial; after max_rejects
+    rejections in a row the solve stops (stalled).
+
+    Returns dict(T, chi2 (at the start and after each kept step), energy (same
+    points), final_chi2, lam, rejected, stalled, status, accepted (per trial))."""
+    edges = np.asarray(edges, dtype=np.int64)
+    T = chain_init(n_nodes, edges, T_meas, gauge) if T_init is None else np.array(T_init, dtype=np.float64)
+    free = np.array([k for k in range(n_nodes) if k != gauge])
+    idx = (7 * free[:, None] + np.arange(7)).ravel()
+    lam, nu = float(lam0), 2.0
+    r2 = edge_r2(T, edges, T_meas, omega)
+    F = huber_energy(r2, huber_delta)
+    chi_hist, F_hist, trials = [float(sum(r2))], [F], []
+    rejected, stalled, status = 0, False, 0
+    for _ in range(iters):
+        H, g, _ = normal_equations(T, edges, T_meas, omega, huber_delta)
+        Hf, gf = H[np.ix_(idx, idx)], g[idx]
+        D = np.diag(Hf).copy()
+        kept = False
+        for _ in range(max_rejects):
+            try:
+                Lc = np.linalg.cholesky(Hf + lam * np.diag(D))
+                dx = -np.linalg.solve(Lc.T, np.linalg.solve(Lc, gf))
+            except np.linalg.LinAlgError:
+                dx = None
+            if dx is not None:
+                pred = 0.5 * float(dx @ (lam * D * dx - gf))
+                Tn = T.copy()
+                for a, node in enumerate(free):
+                    Tn[node] = sim3.exp(dx[7 * a:7 * a + 7]) @ T[node]
+                r2n = edge_r2(Tn, edges, T_meas, omega)
+                Fn = huber_energy(r2n, huber_delta)
+                if pred > 0.0 and Fn < F:
+                    rho = (F - Fn) / pred
+                    lam *= max(1.0 / 3.0, 1.0 - (2.0 * rho - 1.0) ** 3)
+                    nu = 2.0
+                    T, r2, F = Tn, r2n, Fn
+                    trials.append(True)
+                    kept = True
+                    break
+            trials.append(False)
+            rejected += 1
+            lam *= nu
+            nu *= 2.0
+        if not kept:
+            stalled = True
+            break
+        chi_hist.append(float(sum(r2)))
+        F_hist.append(F)
+    return dict(T=T, chi2=chi_hist, energy=F_hist, final_chi2=float(sum(r2)), lam=lam, rejected=rejected,
+                stalled=stalled, status=status, accepted=trials)

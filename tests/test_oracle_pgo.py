@@ -143,3 +143,61 @@ def test_huber_downweights_outlier_edge(rng):
     robust = pgo.pgo_solve(n, E, meas, T_init=Tgt, iters=20, huber_delta=0.01)
     err = lambda T: max(np.abs(rel(T)[k] - rel(Tgt)[k]).max() for k in range(n))
     assert err(robust['T']) < 0.5 * err(plain['T'])
+
+
+# ---- Levenberg-Marquardt (the solver Sec. III-E names)
+
+def test_lm_recovers_truth_from_consistent_measurements(rng):
+    n = 12
+    Tgt = np.array([np.eye(4)] + [rand_pose(rng) for _ in range(n - 1)])
+    E = graph(rng, n, 6)
+    meas = np.array([sim3.inv(Tgt[i]) @ Tgt[j] for i, j in E])
+    init = perturb(rng, Tgt, 0.3)
+    init[0] = Tgt[0]
+    out = pgo.pgo_solve_lm(n, E, meas, T_init=init, iters=40)
+    assert np.abs(rel(out['T']) - rel(Tgt)).max() < 1e-9
+    assert out['final_chi2'] < 1e-18
+
+
+@pytest.mark.parametrize("huber", [np.inf, 0.05])
+def test_lm_energy_never_rises_and_meets_gauss_newton(rng, huber):
+    n = 10
+    E, meas = noisy_problem(rng, n, 5, 0.02)
+    lm = pgo.pgo_solve_lm(n, E, meas, iters=200 if np.isfinite(huber) else 60, huber_delta=huber)
+    F = np.array(lm['energy'])
+    assert np.all(np.diff(F) < 0)  # every kept step lowers the energy
+    assert F[-1] == pytest.approx(pgo.robust_energy(lm['T'], E, meas, huber_delta=huber), rel=1e-12)
+    gn = pgo.pgo_solve(n, E, meas, iters=15 if np.isinf(huber) else 250, huber_delta=huber)
+    assert np.abs(rel(lm['T']) - rel(gn['T'])).max() < 1e-7
+
+
+def test_lm_is_monotone_where_gauss_newton_overshoots(rng):
+    """From a far start undamped Gauss-Newton can raise the energy; LM's kept
+    steps never do (from such a start it may settle in another local minimum,
+    so only the descent is pinned)."""
+    n = 6
+    Tgt = np.array([np.eye(4)] + [rand_pose(rng, 2.0) for _ in range(n - 1)])
+    E = graph(rng, n, 4)
+    meas = np.array([sim3.inv(Tgt[i]) @ Tgt[j] for i, j in E])
+    found = False
+    for seed in range(40):
+        r = np.random.default_rng(seed)
+        init = perturb(r, Tgt, 1.2)
+        init[0] = Tgt[0]
+        gn = pgo.pgo_solve(n, E, meas, T_init=init, iters=1)
+        if pgo.chi2(gn['T'], E, meas) > pgo.chi2(init, E, meas):
+            found = True
+            break
+    assert found, "no overshooting start found"
+    lm = pgo.pgo_solve_lm(n, E, meas, T_init=init, iters=100)
+    assert len(lm['energy']) > 1 and np.all(np.diff(lm['energy']) < 0)
+    assert lm['energy'][-1] < 0.5 * pgo.chi2(init, E, meas)
+
+
+def test_lm_tiny_damping_follows_gauss_newton(rng):
+    n = 8
+    E, meas = noisy_problem(rng, n, 4, 0.01)
+    gn = pgo.pgo_solve(n, E, meas, iters=3)
+    lm = pgo.pgo_solve_lm(n, E, meas, iters=3, lam0=1e-14)
+    assert lm['accepted'][:3] == [True, True, True]
+    assert np.abs(lm['T'] - gn['T']).max() < 1e-9
