@@ -174,27 +174,40 @@ int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* desc, const s3
 
 /* Pose-graph options. */
 #define S3A_PGO_INIT_CHAIN 0x1u /* ignore T on input: chain the edges from the gauge node */
+#define S3A_PGO_LM 0x2u         /* Levenberg-Marquardt (Sec. III-E) instead of fixed-damping Gauss-Newton */
 
 typedef struct {
-  int32_t iters;      /* Gauss-Newton iterations (20) */
+  int32_t iters;      /* outer iterations (20): Gauss-Newton steps, or LM steps kept */
   int32_t gauge;      /* node held fixed (0) */
   double huber_delta; /* Huber threshold on sqrt(e^T Omega e); +inf = none */
-  double lambda;      /* Levenberg damping: H + lambda diag(H); 0 = Gauss-Newton */
+  double lambda;      /* damping along diag(H): fixed for Gauss-Newton (0 = none), the
+                         starting value for LM (0 = 1e-4) */
   uint32_t flags;     /* S3A_PGO_* */
-  int32_t reserved;
+  int32_t max_rejects;/* LM: rejected trials in a row before the solve stops (0 = 10) */
 } s3a_pgo_params;
 
 typedef struct {
-  double chi2[64];        /* sum e^T Omega e at each linearisation point (first 64) */
+  double chi2[64];        /* sum e^T Omega e at each linearisation point (first 64): Gauss-Newton,
+                             before step k; LM, at the start and after each kept step */
   double final_chi2;      /* at the returned poses */
-  int32_t iters;          /* iterations run */
+  int32_t iters;          /* iterations run (LM: steps kept) */
   int32_t status;         /* 0 ok, 2 factorisation failed (graph not connected to the gauge) */
   int64_t factor_nnz_blocks; /* 7x7 blocks in the Cholesky factor (after fill) */
+  double lambda_final;    /* LM: damping after the last trial */
+  int32_t rejected;       /* LM: trials rejected */
+  int32_t stalled;        /* LM: 1 if max_rejects trials in a row were rejected (no lower energy found) */
 } s3a_pgo_report;
 
 /*
- * Sim(3) pose-graph optimisation (Sec. III-E), Gauss-Newton with Huber edge
- * weights and a 7x7-block sparse Cholesky factorisation in FP64 on the GPU.
+ * Sim(3) pose-graph optimisation (Sec. III-E) with Huber edge weights and a
+ * 7x7-block sparse Cholesky factorisation in FP64 on the GPU.
+ * Gauss-Newton (default): exactly iters steps of (H + lambda diag(H)) dx = -g.
+ * S3A_PGO_LM, Levenberg-Marquardt: each trial solves the same system with the
+ * current lambda; it is kept when the energy F = sum rho(sqrt(e^T Omega e))
+ * falls (rho the Huber loss, r^2/2 inside delta), and lambda then scales by
+ * max(1/3, 1 - (2 rho - 1)^3) with rho = (F - F_trial) / predicted reduction
+ * (nu = 2); otherwise the poses are restored, lambda *= nu and nu doubles. The
+ * host reads back each trial's energy (one synchronisation per trial).
  *   ij:     host, 2 * n_edges node indices (i, j) per edge; T_ij maps frame j to
  *           frame i, so a consistent graph has T_j = T_i T_ij.
  *   T_meas: device, n_edges relative similarities T_ij.

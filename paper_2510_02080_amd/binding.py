@@ -15,7 +15,7 @@ F32, BF16 = 0, 1
 OK, EINVAL, EHIP, ENOMEM = 0, -1, -2, -3
 PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE, PAIR_ABORTED = range(6)
 FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
-PGO_INIT_CHAIN = 0x1
+PGO_INIT_CHAIN, PGO_LM = 0x1, 0x2
 
 c_void_p = ctypes.c_void_p
 
@@ -35,12 +35,13 @@ class Tuning(ctypes.Structure):
 
 class PgoParams(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("gauge", ctypes.c_int32), ("huber_delta", ctypes.c_double),
-                ("lam", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+                ("lam", ctypes.c_double), ("flags", ctypes.c_uint32), ("max_rejects", ctypes.c_int32)]
 
 
 class PgoReport(ctypes.Structure):
     _fields_ = [("chi2", ctypes.c_double * 64), ("final_chi2", ctypes.c_double), ("iters", ctypes.c_int32),
-                ("status", ctypes.c_int32), ("factor_nnz_blocks", ctypes.c_int64)]
+                ("status", ctypes.c_int32), ("factor_nnz_blocks", ctypes.c_int64), ("lambda_final", ctypes.c_double),
+                ("rejected", ctypes.c_int32), ("stalled", ctypes.c_int32)]
 
 
 # s3a_align_info, read back as a numpy structured array
@@ -222,7 +223,7 @@ class Handle:
         return gp, gq, gc, gxi
 
     def pose_graph_solve(self, edges, T_meas, T=None, omega=None, iters=20, huber_delta=float("inf"),
-                         lam=0.0, gauge=0, init_chain=None):
+                         lam=0.0, gauge=0, init_chain=None, lm=False, max_rejects=0):
         """edges: (E, 2) int array (host); T_meas: (E, 16) float64 device;
         T: (n, 16) float64 device, updated in place (or created and chained).
         Returns (T, report)."""
@@ -237,8 +238,8 @@ class Handle:
         p.gauge = gauge
         p.huber_delta = huber_delta
         p.lam = lam
-        p.flags = PGO_INIT_CHAIN if init_chain else 0
-        p.reserved = 0
+        p.flags = (PGO_INIT_CHAIN if init_chain else 0) | (PGO_LM if lm else 0)
+        p.max_rejects = max_rejects
         rep = PgoReport()
         _check(self.lib.s3a_pose_graph_solve(self.h, n_nodes, n_edges, edges.ctypes.data_as(c_void_p), _ptr(T_meas),
                                              _ptr(omega), _ptr(T), ctypes.byref(p), ctypes.byref(rep),

@@ -70,6 +70,10 @@ struct PgoDev {
   double* r2;     // [E]     e^T Omega e
   double* chi2;   // [iters + 1]
   int32_t* status;
+  // Levenberg-Marquardt: the undamped system of the last solve and its predicted reduction
+  double* gsave;  // [m][7] right-hand side -g
+  double* dsave;  // [m][7] diagonal of H
+  double* pred;   // [1] dx^T (lambda diag(H) dx - g) / 2
 };
 
 __device__ inline Sim3d ld_pose(const s3a_sim3* p) { return load_sim3(p); }
@@ -170,7 +174,8 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // One Gauss-Newton iteration on one workgroup: chi^2, assembly, factorisation,
 // solves, update. `it` indexes the chi^2 record.
-__global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, double lambda, int it, int update) {
+__global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, double lambda, int it, int update,
+                                                       int lm) {
   __shared__ double sh[PGO_WG / 64 + 1];
   __shared__ int s_fail;
   const int tid = threadIdx.x;
@@ -187,6 +192,7 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     const int c = x / 49, a = x % 49;
     double s = 0.0;
     for (int q = d.dg_ptr[c]; q < d.dg_ptr[c + 1]; ++q) s += d.M[49 * d.dg_edge[q] + a];
+    if (lm && a % 8 == 0) d.dsave[7 * c + a / 8] = s;
     if (lambda > 0.0 && a % 8 == 0) s += lambda * s;
     d.Ld[x] = s;
   }
@@ -201,6 +207,7 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     double s = 0.0;
     for (int q = d.gv_ptr[c]; q < d.gv_ptr[c + 1]; ++q) s += (double)d.gv_sign[q] * d.v[7 * d.gv_edge[q] + a];
     d.g[x] = -s;  // right-hand side -g
+    if (lm) d.gsave[x] = -s;
   }
   __syncthreads();
   // ---- factorisation, level by level
@@ -342,6 +349,13 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     }
     __syncthreads();
   }
+  // ---- LM: reduction the quadratic model predicts, dx^T (lambda D dx - g) / 2 (fixed order)
+  if (lm) {
+    double part2 = 0.0;
+    for (int x = tid; x < d.m * 7; x += PGO_WG) part2 += d.g[x] * (lambda * d.dsave[x] * d.g[x] + d.gsave[x]);
+    const double pr = wg_sum(part2, sh);
+    if (tid == 0) d.pred[0] = 0.5 * pr;
+  }
   // ---- update T <- Exp(dx) T for the free nodes
   for (int c = tid; c < d.m; c += PGO_WG) {
     const int nd = d.node[c];
@@ -359,6 +373,11 @@ struct PgoWorkspace {
   PgoDev dev{};
   int32_t cap_iters = 0;
   int64_t nnz_blocks = 0;
+  // Levenberg-Marquardt: a second linearisation (the trial's) and the poses before a trial
+  double* M_alt = nullptr;
+  double* v_alt = nullptr;
+  double* r2_alt = nullptr;
+  s3a_sim3* T_bak = nullptr;
 };
 
 namespace {
@@ -561,6 +580,120 @@ int fail(int* last_hip, hipError_t e) {
 
 }  // namespace
 
+namespace {
+
+double huber_energy(const std::vector<double>& r2, double delta) {
+  double F = 0.0;
+  for (double x : r2) {
+    const double r = sqrt(x > 0.0 ? x : 0.0);
+    F += r <= delta ? 0.5 * r * r : delta * (r - 0.5 * delta);
+  }
+  return F;
+}
+
+// Levenberg-Marquardt driver: every trial is one damped solve on the device
+// (k_pgo_iterate, which also leaves the predicted reduction), a
+// linearisation at the trial poses into the second buffer set, and a read of
+// the trial's per-edge e^T Omega e to decide on the host.
+int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edges, const s3a_sim3* T_meas,
+                 const double* omega, s3a_sim3* T, const s3a_pgo_params& p, s3a_pgo_report* report, hipStream_t st) {
+  PgoDev cur = ws->dev, trial = ws->dev;
+  trial.M = ws->M_alt;
+  trial.v = ws->v_alt;
+  trial.r2 = ws->r2_alt;
+  const int lg = (n_edges + 127) / 128;
+  const int max_rej = p.max_rejects > 0 ? p.max_rejects : 10;
+  double lam = p.lambda > 0.0 ? p.lambda : 1e-4, nu = 2.0;
+  std::vector<double> r2(n_edges), r2t(n_edges), chi;
+  hipError_t e = hipSuccess;
+  auto linearize = [&](const PgoDev& dd, std::vector<double>& out) -> hipError_t {
+    if (n_edges == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_pgo_linearize, dim3(lg), dim3(128), 0, st, dd, T_meas, omega, T, p.huber_delta, 0);
+    hipError_t ee = hipGetLastError();
+    if (ee == hipSuccess) ee = hipMemcpyAsync(out.data(), dd.r2, sizeof(double) * n_edges, hipMemcpyDeviceToHost, st);
+    if (ee == hipSuccess) ee = hipStreamSynchronize(st);
+    return ee;
+  };
+  auto sum = [](const std::vector<double>& x) {
+    double s = 0.0;
+    for (double v : x) s += v;
+    return s;
+  };
+  if ((e = linearize(cur, r2)) != hipSuccess) return fail(last_hip, e);
+  double F = huber_energy(r2, p.huber_delta);
+  chi.push_back(sum(r2));
+  int kept_steps = 0, rejected = 0, stalled = 0, status = 0;
+  for (int it = 0; it < p.iters && cur.m > 0 && n_edges > 0; ++it) {
+    bool kept = false;
+    for (int rej = 0; rej < max_rej; ++rej) {
+      e = hipMemcpyAsync(ws->T_bak, T, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
+      if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<uint32_t*>(cur.status), 1, st);
+      if (e != hipSuccess) return fail(last_hip, e);
+      hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, cur, T, lam, it, 1, 1);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+      int32_t fst = 0;
+      double pred = 0.0;
+      e = hipMemcpyAsync(&fst, cur.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipMemcpyAsync(&pred, cur.pred, sizeof(double), hipMemcpyDeviceToHost, st);
+      if (e == hipSuccess) e = hipStreamSynchronize(st);
+      if (e != hipSuccess) return fail(last_hip, e);
+      status = fst;
+      if (fst == 0) {
+        if ((e = linearize(trial, r2t)) != hipSuccess) return fail(last_hip, e);
+        const double Ft = huber_energy(r2t, p.huber_delta);
+        if (pred > 0.0 && Ft < F) {
+          const double rho = (F - Ft) / pred;
+          const double f = 1.0 - (2.0 * rho - 1.0) * (2.0 * rho - 1.0) * (2.0 * rho - 1.0);
+          lam *= f > 1.0 / 3.0 ? f : 1.0 / 3.0;
+          nu = 2.0;
+          std::swap(cur.M, trial.M);
+          std::swap(cur.v, trial.v);
+          std::swap(cur.r2, trial.r2);
+          r2.swap(r2t);
+          F = Ft;
+          kept = true;
+          break;
+        }
+      }
+      // rejected: restore the poses, raise the damping
+      e = hipMemcpyAsync(T, ws->T_bak, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
+      if (e != hipSuccess) return fail(last_hip, e);
+      ++rejected;
+      lam *= nu;
+      nu *= 2.0;
+    }
+    if (!kept) {
+      stalled = 1;
+      break;
+    }
+    status = 0;
+    ++kept_steps;
+    chi.push_back(sum(r2));
+  }
+  // the linearisation buffers the workspace names are the ones kept last
+  ws->dev.M = cur.M;
+  ws->dev.v = cur.v;
+  ws->dev.r2 = cur.r2;
+  ws->M_alt = trial.M;
+  ws->v_alt = trial.v;
+  ws->r2_alt = trial.r2;
+  if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(last_hip, e);
+  if (report) {
+    memset(report, 0, sizeof(*report));
+    for (size_t i = 0; i < chi.size() && i < 64; ++i) report->chi2[i] = chi[i];
+    report->final_chi2 = chi.back();
+    report->iters = kept_steps;
+    report->status = stalled ? status : 0;
+    report->factor_nnz_blocks = ws->nnz_blocks;
+    report->lambda_final = lam;
+    report->rejected = rejected;
+    report->stalled = stalled;
+  }
+  return S3A_OK;
+}
+
+}  // namespace
+
 void pgo_free(PgoWorkspace* ws) {
   if (!ws) return;
   if (ws->buf) (void)hipFree(ws->buf);
@@ -580,7 +713,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
   }
   if (n_nodes < 1 || n_edges < 0 || !T || (n_edges > 0 && (!ij || !T_meas))) return S3A_EINVAL;
   if (p.iters < 0 || p.iters > 1000 || p.gauge < 0 || p.gauge >= n_nodes) return S3A_EINVAL;
-  if (!(p.huber_delta > 0.0) || !(p.lambda >= 0.0) || (p.flags & ~S3A_PGO_INIT_CHAIN) || p.reserved != 0)
+  if (!(p.huber_delta > 0.0) || !(p.lambda >= 0.0) || !(p.lambda < 1e300) ||
+      (p.flags & ~(S3A_PGO_INIT_CHAIN | S3A_PGO_LM)) || p.max_rejects < 0 || p.max_rejects > 1000)
     return S3A_EINVAL;
   for (int k = 0; k < n_edges; ++k) {
     const int i = ij[2 * k], j = ij[2 * k + 1];
@@ -610,6 +744,9 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<double>(49 * (size_t)m) + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<double>(iters_cap) + bytes_of<int32_t>(4);
+    total += bytes_of<double>(7 * (size_t)m + 7) * 2 + bytes_of<double>(8);  // LM: gsave, dsave, pred
+    total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
+    total += bytes_of<s3a_sim3>(n_nodes);
     if (ws->buf) {
       (void)hipStreamSynchronize(st);
       (void)hipFree(ws->buf);
@@ -663,6 +800,13 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     d.r2 = carve<double>(c, E + 1);
     d.chi2 = carve<double>(c, iters_cap);
     d.status = carve<int32_t>(c, 4);
+    d.gsave = carve<double>(c, 7 * (size_t)m + 7);
+    d.dsave = carve<double>(c, 7 * (size_t)m + 7);
+    d.pred = carve<double>(c, 8);
+    ws->M_alt = carve<double>(c, 49 * (size_t)E + 49);
+    ws->v_alt = carve<double>(c, 7 * (size_t)E + 7);
+    ws->r2_alt = carve<double>(c, E + 1);
+    ws->T_bak = carve<s3a_sim3>(c, n_nodes);
     for (auto& u : up) {
       e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return fail(last_hip, e);
@@ -684,6 +828,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
   }
   const int lg = (n_edges + 127) / 128;
+  if (p.flags & S3A_PGO_LM) return pgo_solve_lm(ws, last_hip, n_nodes, n_edges, T_meas, omega, T, p, report, st);
   for (int it = 0; it <= p.iters; ++it) {
     const int update = it < p.iters;
     if (n_edges > 0) {
@@ -691,7 +836,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
       if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
     }
     if (update && d.m == 0) continue;
-    hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, d, T, p.lambda, it, update);
+    hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, d, T, p.lambda, it, update, 0);
     if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
   }
   if (report) {

@@ -137,3 +137,51 @@ def test_full_loop_closure_graph(h):
     H, g, c2 = pgo.normal_equations(T20, E, meas)
     assert np.abs(g[7:]).max() < 1e-9 * max(1.0, np.abs(H).max())
     assert rep20.final_chi2 <= rep20.chi2[0]
+
+
+# ---- Levenberg-Marquardt (S3A_PGO_LM)
+
+@pytest.mark.parametrize("case", ["plain", "huber", "far"])
+def test_lm_matches_oracle(h, case):
+    """Same trials as the oracle's LM (kept / rejected, damping, chi^2 after
+    each kept step) and the same poses; 'far' starts where undamped steps
+    overshoot, so trials get rejected."""
+    rng = np.random.default_rng({"plain": 11, "huber": 12, "far": 14}[case])
+    n = 16
+    E, meas, Tgt = small_graph(rng, n, 8, 0.03)
+    # stop while every kept step still lowers the energy well above rounding,
+    # so that both sides take the same accept / reject decisions
+    iters = {"plain": 3, "huber": 6, "far": 8}[case]
+    kw, okw = dict(iters=iters), dict(iters=iters)
+    T0 = None
+    if case == "huber":
+        kw["huber_delta"] = okw["huber_delta"] = 0.05
+    if case == "far":
+        T0 = np.array([sim3.exp(1.6 * rng.normal(size=7)) @ T for T in Tgt])
+        T0[0] = Tgt[0]
+        okw["T_init"] = T0
+    T, rep = run_gpu(h, E, meas, n, T0=T0, lm=True, **kw)
+    ref = pgo.pgo_solve_lm(n, E, meas, **okw)
+    F = np.array(ref["energy"])
+    assert np.all(-np.diff(F) > 1e-9 * F[:-1]), "test reaches the rounding floor"
+    kept = len(ref["chi2"]) - 1
+    assert rep.status == 0 and rep.iters == kept and rep.rejected == ref["rejected"]
+    assert bool(rep.stalled) == ref["stalled"]
+    assert np.allclose(np.array(rep.chi2[:kept + 1]), ref["chi2"], rtol=1e-8, atol=1e-14)
+    assert rep.lambda_final == pytest.approx(ref["lam"], rel=1e-6)
+    assert pose_err(T, ref["T"]) <= TOL
+    if case == "far":
+        assert ref["rejected"] > 0
+
+
+def test_lm_full_loop_closure_graph(h):
+    """1000 nodes: every kept step lowers chi^2 (no Huber: the energy is
+    chi^2 / 2), and the result is the Gauss-Newton minimum."""
+    E, Tgt = synth.config4_graph()
+    meas = noisy_measurements(Tgt, E, sigma=1e-3)
+    T, rep = run_gpu(h, E, meas, 1000, iters=20, lm=True)
+    assert rep.status == 0 and rep.iters >= 1
+    chi = np.array(rep.chi2[:rep.iters + 1])
+    assert np.all(np.diff(chi) < 0)
+    H, g, _ = pgo.normal_equations(T, E, meas)
+    assert np.abs(g[7:]).max() < 1e-8 * max(1.0, np.abs(H).max())
