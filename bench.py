@@ -320,6 +320,17 @@ def main():
                                chi2_first=rep.chi2[0], chi2_final=rep.final_chi2, status=rep.status,
                                factor_blocks=int(rep.factor_nnz_blocks))
         log(f"pgo: {ms_pgo:.2f} ms per 20-iteration solve, chi2 {rep.chi2[0]:.4g} -> {rep.final_chi2:.4g}")
+        # Levenberg-Marquardt, the optimiser the paper names: up to 20 kept steps
+        h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True, lm=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(reps):
+            _, rl = h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True, lm=True)
+        ms_lm = (time.perf_counter() - t) / reps * 1e3
+        res["pgo_lm_fp64"] = dict(ms_per_solve=ms_lm, kept_steps=rl.iters, rejected=rl.rejected, stalled=rl.stalled,
+                                  chi2_first=rl.chi2[0], chi2_final=rl.final_chi2, lambda_final=rl.lambda_final)
+        log(f"pgo LM: {ms_lm:.2f} ms ({rl.iters} kept, {rl.rejected} rejected), chi2 {rl.chi2[0]:.4g} -> "
+            f"{rl.final_chi2:.4g}")
 
     # ---- CPU baseline: the oracle as it stands, one core, bounded sample
     cpu = None

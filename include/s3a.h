@@ -207,7 +207,10 @@ typedef struct {
  * falls (rho the Huber loss, r^2/2 inside delta), and lambda then scales by
  * max(1/3, 1 - (2 rho - 1)^3) with rho = (F - F_trial) / predicted reduction
  * (nu = 2); otherwise the poses are restored, lambda *= nu and nu doubles. The
- * host reads back each trial's energy (one synchronisation per trial).
+ * solve stops after iters kept steps, after max_rejects rejections in a row
+ * (stalled), or when a trial's predicted reduction is at most 1e-15 F
+ * (converged). The host reads back each trial's energy (one synchronisation
+ * per trial).
  *   ij:     host, 2 * n_edges node indices (i, j) per edge; T_ij maps frame j to
  *           frame i, so a consistent graph has T_j = T_i T_ij.
  *   T_meas: device, n_edges relative similarities T_ij.

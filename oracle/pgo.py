@@ -165,10 +165,12 @@ def pgo_solve_lm(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20, hube
     update). A rejected trial (energy not lower, or the damped matrix not
     positive definite) restores the poses and multiplies lambda by nu, then
     doubles nu. An iteration ends at its first kept trial; after max_rejects
-    rejections in a row the solve stops (stalled).
+    rejections in a row the solve stops (stalled). It also stops, converged,
+    when a trial's predicted reduction is at most 1e-15 F, below what F can resolve.
 
     Returns dict(T, chi2 (at the start and after each kept step), energy (same
-    points), final_chi2, lam, rejected, stalled, status, accepted (per trial))."""
+    points), final_chi2, lam, rejected, stalled, converged, status, accepted
+    (per trial))."""
     edges = np.asarray(edges, dtype=np.int64)
     T = chain_init(n_nodes, edges, T_meas, gauge) if T_init is None else np.array(T_init, dtype=np.float64)
     free = np.array([k for k in range(n_nodes) if k != gauge])
@@ -177,7 +179,7 @@ def pgo_solve_lm(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20, hube
     r2 = edge_r2(T, edges, T_meas, omega)
     F = huber_energy(r2, huber_delta)
     chi_hist, F_hist, trials = [float(sum(r2))], [F], []
-    rejected, stalled, status = 0, False, 0
+    rejected, stalled, status, converged = 0, False, 0, False
     for _ in range(iters):
         H, g, _ = normal_equations(T, edges, T_meas, omega, huber_delta)
         Hf, gf = H[np.ix_(idx, idx)], g[idx]
@@ -191,6 +193,9 @@ def pgo_solve_lm(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20, hube
                 dx = None
             if dx is not None:
                 pred = 0.5 * float(dx @ (lam * D * dx - gf))
+                if pred <= 1e-15 * F:
+                    converged = True
+                    break
                 Tn = T.copy()
                 for a, node in enumerate(free):
                     Tn[node] = sim3.exp(dx[7 * a:7 * a + 7]) @ T[node]
@@ -208,10 +213,12 @@ def pgo_solve_lm(n_nodes, edges, T_meas, omega=None, T_init=None, iters=20, hube
             rejected += 1
             lam *= nu
             nu *= 2.0
+        if converged:
+            break
         if not kept:
             stalled = True
             break
         chi_hist.append(float(sum(r2)))
         F_hist.append(F)
     return dict(T=T, chi2=chi_hist, energy=F_hist, final_chi2=float(sum(r2)), lam=lam, rejected=rejected,
-                stalled=stalled, status=status, accepted=trials)
+                stalled=stalled, converged=converged, status=status, accepted=trials)

@@ -215,35 +215,50 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     const int c0 = d.lev_ptr[l], c1 = d.lev_ptr[l + 1];
     // (A) every update target of this level (diagonal and off-diagonal blocks of
     // its columns): one wavefront per target, lane = element (r, s) of the 7x7
-    // block: S -= sum_k L_a L_b^T over the target's update list (in order; two
-    // updates in flight so their loads overlap).
+    // block: S -= sum_k L_a L_b^T over the target's update list, in list order.
+    // The list's block indices are fetched 64 at a time, one per lane, and read
+    // back from lanes (uniform), so the only dependent loads left are the
+    // blocks themselves; four updates are in flight.
     {
       const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
       const int lane = tid & 63, wv = tid >> 6;
-      const int r = lane / 7, s = lane % 7;
+      const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
       for (int ti = wv; ti < nt; ti += PGO_WG / 64) {
         const int target = d.lt_tgt[t0 + ti];
         const int q0 = d.up_ptr[target], q1 = d.up_ptr[target + 1];
-        double acc0 = 0.0, acc1 = 0.0;
-        if (lane < 49) {
-          int q = q0;
-          for (; q + 2 <= q1; q += 2) {
-            const double* A0 = d.Lb + 49 * d.up_a[q] + 7 * r;
-            const double* B0 = d.Lb + 49 * d.up_b[q] + 7 * s;
-            const double* A1 = d.Lb + 49 * d.up_a[q + 1] + 7 * r;
-            const double* B1 = d.Lb + 49 * d.up_b[q + 1] + 7 * s;
-            for (int u = 0; u < 7; ++u) {
-              acc0 += A0[u] * B0[u];
-              acc1 += A1[u] * B1[u];
+        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+        for (int qb = q0; qb < q1; qb += 64) {
+          const int nq = min(64, q1 - qb);
+          const int ia = lane < nq ? d.up_a[qb + lane] : 0;
+          const int ib = lane < nq ? d.up_b[qb + lane] : 0;
+          int u = 0;
+          for (; u + 4 <= nq; u += 4) {
+            const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
+            const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
+            const double* A1 = d.Lb + 49 * __shfl(ia, u + 1, 64) + 7 * r;
+            const double* B1 = d.Lb + 49 * __shfl(ib, u + 1, 64) + 7 * s;
+            const double* A2 = d.Lb + 49 * __shfl(ia, u + 2, 64) + 7 * r;
+            const double* B2 = d.Lb + 49 * __shfl(ib, u + 2, 64) + 7 * s;
+            const double* A3 = d.Lb + 49 * __shfl(ia, u + 3, 64) + 7 * r;
+            const double* B3 = d.Lb + 49 * __shfl(ib, u + 3, 64) + 7 * s;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) {
+              acc0 += A0[k] * B0[k];
+              acc1 += A1[k] * B1[k];
+              acc2 += A2[k] * B2[k];
+              acc3 += A3[k] * B3[k];
             }
           }
-          if (q < q1) {
-            const double* A0 = d.Lb + 49 * d.up_a[q] + 7 * r;
-            const double* B0 = d.Lb + 49 * d.up_b[q] + 7 * s;
-            for (int u = 0; u < 7; ++u) acc0 += A0[u] * B0[u];
+          for (; u < nq; ++u) {
+            const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
+            const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
+#pragma unroll
+            for (int k = 0; k < 7; ++k) acc0 += A0[k] * B0[k];
           }
+        }
+        if (lane < 49) {
           double* dst = target < d.m ? d.Ld + 49 * target + lane : d.Lb + 49 * (target - d.m) + lane;
-          *dst -= acc0 + acc1;
+          *dst -= (acc0 + acc1) + (acc2 + acc3);
         }
       }
     }
@@ -622,7 +637,7 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
   if ((e = linearize(cur, r2)) != hipSuccess) return fail(last_hip, e);
   double F = huber_energy(r2, p.huber_delta);
   chi.push_back(sum(r2));
-  int kept_steps = 0, rejected = 0, stalled = 0, status = 0;
+  int kept_steps = 0, rejected = 0, stalled = 0, converged = 0, status = 0;
   for (int it = 0; it < p.iters && cur.m > 0 && n_edges > 0; ++it) {
     bool kept = false;
     for (int rej = 0; rej < max_rej; ++rej) {
@@ -638,6 +653,12 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
       if (e == hipSuccess) e = hipStreamSynchronize(st);
       if (e != hipSuccess) return fail(last_hip, e);
       status = fst;
+      if (fst == 0 && pred <= 1e-15 * F) {  // below what F resolves: converged
+        e = hipMemcpyAsync(T, ws->T_bak, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
+        if (e != hipSuccess) return fail(last_hip, e);
+        converged = 1;
+        break;
+      }
       if (fst == 0) {
         if ((e = linearize(trial, r2t)) != hipSuccess) return fail(last_hip, e);
         const double Ft = huber_energy(r2t, p.huber_delta);
@@ -662,6 +683,7 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
       lam *= nu;
       nu *= 2.0;
     }
+    if (converged) break;
     if (!kept) {
       stalled = 1;
       break;
