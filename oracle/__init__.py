@@ -15,6 +15,8 @@ umeyama  : weighted Umeyama closed form (Sec. III-C.2, eq. (sim3))
 irls     : confidence mask/weights + Umeyama start + Huber IRLS Gauss-Newton
 cost     : Huber-weighted alignment cost, its analytic gradient, and central
            finite differences
+implicit : derivative of the solved pose with respect to the points and
+           confidences (implicit function theorem, exact Huber Hessian)
 pgo      : dense Gauss-Newton Sim(3) pose-graph solve (Sec. III-E)
 points   : point correction: submap points to the world frame, sparse-map
            replacement (Sec. III-C.3)
