@@ -172,6 +172,36 @@ int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* desc, const s3
                              float* gpx, float* gpy, float* gpz, float* gqx, float* gqy, float* gqz,
                              float* gc, double* gxi, s3a_stream stream);
 
+/*
+ * Implicit derivative of the solved pose (differentiating through the
+ * alignment): S_k is taken as a stationary point of the Huber cost
+ * L_k(xi) = sum_i w_i rho_delta(|Exp(xi) S_k p_i - q_i|) at xi = 0. With
+ * F = dL/dxi and H = d^2 L/dxi^2 there (the exact Hessian: Huber curvature
+ * and the second-order terms of Exp included, not the Gauss-Newton matrix),
+ * the implicit function theorem gives, for a loss l(S),
+ *   dl/dtheta = -(dF/dtheta)^T v,  v = H^{-1} dl/dxi,
+ * over theta = (p_i, q_i, c_i). Per valid point, with y = S p, r = y - q,
+ * psi = rho'(e)/e, a = J(y) v = v_rho + v_omega x y + v_sigma y and
+ * b = psi (a - [e > delta] (a . r/e) r/e):
+ *   dl/dq_i = (c_i/C) b,  dl/dp_i = -(c_i/C) (sR)^T (b + psi (r x v_omega + v_sigma r)),
+ *   dl/dc_i = -(psi a . r - v^T F) / C;  zero for masked points.
+ *   S:     device, n_pairs solutions (typically s3a_align_pairs' output).
+ *   gS:    device, dl/dS per pair: 16 doubles in s3a_sim3 layout (d/dR row-major,
+ *          d/dt, d/ds; pad ignored), or with S3A_IMPLICIT_TANGENT 7 doubles
+ *          d l/d xi of a left perturbation S -> Exp(xi) S.
+ *   gpx..gc: device FP32 planes of n_points, 16-byte aligned (NULL = not
+ *          wanted); entries outside every pair's range are left untouched.
+ *   v_out: device, 7 * n_pairs doubles (v, NaN for a failed pair), or NULL.
+ *   status_out: device, n_pairs int32 (S3A_PAIR_OK, EMPTY, DEGENERATE when H is
+ *          not positive definite, BADRANGE), or NULL. Failed pairs get zero
+ *          gradients.
+ */
+#define S3A_IMPLICIT_TANGENT 0x1u
+int s3a_align_pairs_implicit_backward(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* S,
+                                      const double* gS, uint32_t flags, float* gpx, float* gpy, float* gpz,
+                                      float* gqx, float* gqy, float* gqz, float* gc, double* v_out,
+                                      int32_t* status_out, s3a_stream stream);
+
 /* Pose-graph options. */
 #define S3A_PGO_INIT_CHAIN 0x1u /* ignore T on input: chain the edges from the gauge node */
 #define S3A_PGO_LM 0x2u         /* Levenberg-Marquardt (Sec. III-E) instead of fixed-damping Gauss-Newton */

@@ -40,56 +40,46 @@ from .irls import huber_psi, valid_mask
 
 OK, EMPTY, DEGENERATE = 0, 1, 2
 
-_GEN = [sim3.hat(np.eye(7)[a]) for a in range(7)]
+_GEN = np.array([sim3.hat(np.eye(7)[a]) for a in range(7)])  # (7, 4, 4) generators G_a
+# (G_a G_b + G_b G_a) / 2: the second derivative of Exp(xi) [y; 1] at xi = 0
+_SYM2 = np.array([[0.5 * (_GEN[a] @ _GEN[b] + _GEN[b] @ _GEN[a]) for b in range(7)] for a in range(7)])
 
 
-def _second_order(y):
-    """T[k, a, b] = d^2 (Exp(xi) y)_k / dxi_a dxi_b at xi = 0."""
-    yh = np.r_[y, 1.0]
-    T = np.zeros((3, 7, 7))
-    for a in range(7):
-        for b in range(7):
-            T[:, a, b] = (0.5 * (_GEN[a] @ _GEN[b] + _GEN[b] @ _GEN[a]) @ yh)[:3]
-    return T
-
-
-def _jacobian(y):
-    """dr/dxi at xi = 0, column a = G_a [y; 1] (top three rows)."""
-    yh = np.r_[y, 1.0]
-    return np.stack([(_GEN[a] @ yh)[:3] for a in range(7)], axis=1)
-
-
-def _huber_hessian(r, delta):
-    e = np.linalg.norm(r)
-    if e <= delta:
-        return np.eye(3)
-    u = r / e
-    return (delta / e) * (np.eye(3) - np.outer(u, u))
+def _pieces(p, q, c, T, tau, delta):
+    """Valid points' weights, y, r, psi, homogeneous y, J (n, 3, 7), Q (n, 3, 3)."""
+    m, _ = valid_mask(p, q, c, tau)
+    C = float(c[m].sum())
+    y = T[:3, :3] @ p[m].T
+    y = y.T + T[:3, 3]
+    r = y - q[m]
+    e = np.linalg.norm(r, axis=1)
+    psi = huber_psi(e, delta)
+    yh = np.c_[y, np.ones(len(y))]
+    J = np.einsum('aij,nj->nia', _GEN[:, :3, :], yh)  # column a = G_a [y; 1]
+    u = r / np.where(e > 0, e, 1.0)[:, None]
+    outside = (e > delta)[:, None, None]
+    Q = np.where(outside, psi[:, None, None] * (np.eye(3) - np.einsum('ni,nj->nij', u, u)), np.eye(3))
+    w = c[m] / C if C > 0 else np.zeros(int(m.sum()))
+    return m, C, w, y, r, psi, yh, J, Q
 
 
 def hessian_and_gradient(p, q, c, T, tau=0.0, delta=0.05):
     """(H, F, C, valid mask) of L at xi = 0."""
     p, q, c = (np.asarray(a, dtype=np.float64) for a in (p, q, c))
-    m, _ = valid_mask(p, q, c, tau)
-    C = float(c[m].sum())
-    H, F = np.zeros((7, 7)), np.zeros(7)
+    m, C, w, y, r, psi, yh, J, Q = _pieces(p, q, c, T, tau, delta)
     if not C > 0.0:
-        return H, F, C, m
-    for i in np.flatnonzero(m):
-        w = c[i] / C
-        y = T[:3, :3] @ p[i] + T[:3, 3]
-        r = y - q[i]
-        e = np.linalg.norm(r)
-        psi = float(huber_psi(np.array([e]), delta)[0])
-        J = _jacobian(y)
-        H += w * (J.T @ _huber_hessian(r, delta) @ J + np.einsum('k,kab->ab', psi * r, _second_order(y)))
-        F += w * psi * (J.T @ r)
+        return np.zeros((7, 7)), np.zeros(7), C, m
+    H = np.einsum('n,nia,nij,njb->ab', w, J, Q, J)
+    # sum_n w psi r_k (d^2 (Exp(xi) y)_k / dxi_a dxi_b) = sum_{k,l} SYM2[a, b, k, l] sum_n w psi r_k yh_l
+    H += np.einsum('abkl,kl->ab', _SYM2[:, :, :3, :], np.einsum('n,nk,nl->kl', w * psi, r, yh))
+    F = np.einsum('n,nia,ni->a', w * psi, J, r)
     return H, F, C, m
 
 
-def implicit_grad(p, q, c, T, gS, tau=0.0, delta=0.05):
+def implicit_grad(p, q, c, T, gS, tau=0.0, delta=0.05, rows=None):
     """dl/dp, dl/dq (N, 3), dl/dc (N,), v, H, F, status for one pair at the
-    solution T (4x4), given gS = dl/dxi* (7,)."""
+    solution T (4x4), given gS = dl/dxi* (7,). rows: restrict the per-point
+    outputs to these rows (the rest stay zero)."""
     p, q, c = (np.asarray(a, dtype=np.float64) for a in (p, q, c))
     n = len(p)
     gp, gq, gc = np.zeros((n, 3)), np.zeros((n, 3)), np.zeros(n)
@@ -102,20 +92,19 @@ def implicit_grad(p, q, c, T, gS, tau=0.0, delta=0.05):
     except np.linalg.LinAlgError:
         return dict(out, status=DEGENERATE)
     v = np.linalg.solve(H, np.asarray(gS, dtype=np.float64))
-    K = sim3.skew(v[3:6]) + v[6] * np.eye(3)
-    sR = T[:3, :3]
-    vF = float(v @ F)
-    for i in np.flatnonzero(m):
-        w = c[i] / C
-        y = sR @ p[i] + T[:3, 3]
-        r = y - q[i]
-        e = np.linalg.norm(r)
-        psi = float(huber_psi(np.array([e]), delta)[0])
-        a = _jacobian(y) @ v
-        Qa = _huber_hessian(r, delta) @ a
-        gq[i] = w * Qa
-        gp[i] = -w * sR.T @ (Qa + K.T @ (psi * r))
-        gc[i] = -(psi * float(a @ r) - vF) / C
+    K = sim3.skew(v[3:6]) + v[6] * np.eye(3)  # d(J(y) v)/dy
+    sel = m.copy()
+    if rows is not None:
+        keep = np.zeros(n, dtype=bool)
+        keep[np.asarray(rows)] = True
+        sel &= keep
+    mv, _, w, y, r, psi, yh, J, Q = _pieces(p[sel], q[sel], c[sel], T, tau, delta)
+    w = c[sel] / C
+    a = np.einsum('nia,a->ni', J, v)
+    Qa = np.einsum('nij,nj->ni', Q, a)
+    gq[sel] = w[:, None] * Qa
+    gp[sel] = -w[:, None] * (Qa + (psi[:, None] * r) @ K) @ T[:3, :3]
+    gc[sel] = -(psi * np.einsum('ni,ni->n', a, r) - float(v @ F)) / C
     return dict(out, v=v, status=OK)
 
 

@@ -11,7 +11,7 @@ fallback.
 from .binding import (BF16, F32, FLAG_FINAL_COST, FLAG_PERSISTENT, FLAG_NO_GRAPH, FLAG_PLAIN, INFO_DTYPE,
                       PAIR_ABORTED, PAIR_BADRANGE, PAIR_DEGENERATE, PAIR_EMPTY, PAIR_NONFINITE, PAIR_OK, Handle, Pointmaps,
                       S3AError, info_to_numpy, load_library, sim3_from_numpy, sim3_to_numpy)
-from .autograd import AlignCost, align_cost as align_cost_autograd
+from .autograd import AlignCost, AlignSolve, align_cost as align_cost_autograd, align_solve
 
 _handles = {}
 
@@ -33,6 +33,10 @@ def align_cost(pm, S, xi, tau, delta=0.05):
 
 def align_pairs_backward(pm, S, xi, L, C, gL, tau, delta=0.05, need=(True, True, True, True)):
     return handle(pm.device.index or 0).align_pairs_backward(pm, S, xi, L, C, gL, tau, delta, need)
+
+
+def align_pairs_implicit_backward(pm, S, gS, tau, delta=0.05, tangent=False, need=(True, True, True)):
+    return handle(pm.device.index or 0).align_pairs_implicit_backward(pm, S, gS, tau, delta, tangent, need)
 
 
 def pose_graph_solve(edges, T_meas, T=None, **kw):

@@ -16,6 +16,7 @@ OK, EINVAL, EHIP, ENOMEM = 0, -1, -2, -3
 PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE, PAIR_ABORTED = range(6)
 FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 PGO_INIT_CHAIN, PGO_LM = 0x1, 0x2
+IMPLICIT_TANGENT = 0x1
 
 c_void_p = ctypes.c_void_p
 
@@ -70,6 +71,8 @@ _EXPORTS = {
     "s3a_correct_points": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, ctypes.c_int64, c_void_p,
                                           c_void_p, c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),
+    "s3a_align_pairs_implicit_backward": (ctypes.c_int, [c_void_p, ctypes.POINTER(AlignDesc), c_void_p, c_void_p,
+                                                         ctypes.c_uint32] + [c_void_p] * 9 + [c_void_p]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -221,6 +224,29 @@ class Handle:
         _check(self.lib.s3a_align_pairs_backward(self.h, ctypes.byref(d), _ptr(S), _ptr(xi), _ptr(L), _ptr(C),
                                                  _ptr(gL), *gps, *gqs, _ptr(gc), _ptr(gxi), _stream(dev)), self.h)
         return gp, gq, gc, gxi
+
+    def align_pairs_implicit_backward(self, pm, S, gS, tau, delta=0.05, tangent=False, need=(True, True, True)):
+        """Derivative of the solved poses S through the implicit function
+        theorem. gS: (n, 16) float64 device (d/dS in s3a_sim3 layout) or, with
+        tangent=True, (n, 7) (d/dxi of a left perturbation). need = (points p,
+        points q, confidences). Returns (gp (3, N) | None, gq (3, N) | None,
+        gc (N) | None, v (n, 7) float64, status (n,) int32)."""
+        N = pm.n_points
+        Np = (N + 3) // 4 * 4
+        dev = pm.device
+        alloc = torch.empty if pm.covers_all else torch.zeros
+        gp = alloc((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[0] else None
+        gq = alloc((3, Np), dtype=torch.float32, device=dev)[:, :N] if need[1] else None
+        gc = alloc(N, dtype=torch.float32, device=dev) if need[2] else None
+        v = torch.empty((pm.n_pairs, 7), dtype=torch.float64, device=dev)
+        status = torch.empty(pm.n_pairs, dtype=torch.int32, device=dev)
+        d = pm.desc(tau, delta, 0)
+        gps = [_ptr(gp[i]) if gp is not None else None for i in range(3)]
+        gqs = [_ptr(gq[i]) if gq is not None else None for i in range(3)]
+        _check(self.lib.s3a_align_pairs_implicit_backward(self.h, ctypes.byref(d), _ptr(S), _ptr(gS),
+                                                          IMPLICIT_TANGENT if tangent else 0, *gps, *gqs, _ptr(gc),
+                                                          _ptr(v), _ptr(status), _stream(dev)), self.h)
+        return gp, gq, gc, v, status
 
     def pose_graph_solve(self, edges, T_meas, T=None, omega=None, iters=20, huber_delta=float("inf"),
                          lam=0.0, gauge=0, init_chain=None, lm=False, max_rejects=0):

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
-HIP_SOURCES = ["api.hip", "align.hip", "adjoint.hip", "persistent.hip", "pgo.hip", "points.hip"]
+HIP_SOURCES = ["api.hip", "align.hip", "adjoint.hip", "persistent.hip", "pgo.hip", "points.hip", "implicit.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

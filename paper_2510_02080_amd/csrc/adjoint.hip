@@ -11,24 +11,6 @@
 
 namespace s3a {
 
-// Gradients are written once and not read back by the library: streaming
-// (non-temporal) global stores.
-__device__ inline void store_vec(float* base, int64_t g0, int64_t n, const float* v, int VEC, int64_t lo,
-                                 int64_t hi) {
-  if (!base) return;
-  if (g0 >= lo && g0 + VEC <= hi && g0 + VEC <= n) {
-    for (int e = 0; e < VEC; e += 4) {
-      const s3a_f4 x = {v[e], v[e + 1], v[e + 2], v[e + 3]};
-      __builtin_nontemporal_store(x, (S3A_GLOBAL s3a_f4*)(base + g0 + e));
-    }
-  } else {
-    for (int e = 0; e < VEC; ++e) {
-      const int64_t g = g0 + e;
-      if (g >= lo && g < hi && g < n) base[g] = v[e];
-    }
-  }
-}
-
 template <int DT, int WG, int ITEMS>
 __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __restrict__ cd, Work w) {
   constexpr int VEC = Planes<DT>::VEC;
@@ -104,7 +86,7 @@ __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __rest
         acc[6] += y[0] * orr[0] + y[1] * orr[1] + y[2] * orr[2];
       }
 #pragma unroll
-      for (int j = 0; j < 7; ++j) store_vec(gout[j], g0, sh.n_points, go[j], VEC, td.lo, td.end);
+      for (int j = 0; j < 7; ++j) store_grad_vec(gout[j], g0, sh.n_points, go[j], VEC, td.lo, td.end);
     }
     block_store_f64<WG, 7>(acc, red, w.partials + (int64_t)t * NSTAT);
   }

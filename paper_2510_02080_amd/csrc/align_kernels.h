@@ -77,6 +77,24 @@ struct Planes<S3A_BF16> {
   }
 };
 
+// Gradients are written once and not read back by the library: streaming
+// (non-temporal) global stores.
+__device__ inline void store_grad_vec(float* base, int64_t g0, int64_t n, const float* v, int VEC, int64_t lo,
+                                 int64_t hi) {
+  if (!base) return;
+  if (g0 >= lo && g0 + VEC <= hi && g0 + VEC <= n) {
+    for (int e = 0; e < VEC; e += 4) {
+      const s3a_f4 x = {v[e], v[e + 1], v[e + 2], v[e + 3]};
+      __builtin_nontemporal_store(x, (S3A_GLOBAL s3a_f4*)(base + g0 + e));
+    }
+  } else {
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t g = g0 + e;
+      if (g >= lo && g < hi && g < n) base[g] = v[e];
+    }
+  }
+}
+
 __device__ inline bool finite7(const float* x) {
   bool f = true;
 #pragma unroll

@@ -10,6 +10,7 @@
 #include "align_launch.h"
 #include "pgo.h"
 #include "points.h"
+#include "implicit.h"
 
 using namespace s3a;
 
@@ -59,6 +60,8 @@ struct s3a_handle {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
   int32_t* flags_dev = nullptr;  // small device scratch (offset-check flag of the point transform)
+  double* hpart = nullptr;       // per-tile sums of the implicit-derivative pass
+  int64_t hpart_tiles = 0;
 };
 
 namespace {
@@ -336,6 +339,7 @@ int s3a_destroy(s3a_handle* h) {
   clear_graphs(h);
   if (h->ws) (void)hipFree(h->ws);
   if (h->flags_dev) (void)hipFree(h->flags_dev);
+  if (h->hpart) (void)hipFree(h->hpart);
   pgo_free(h->pgo);
   for (auto& ev : h->ev_used) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   for (auto& ev : h->ev_free) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
@@ -513,6 +517,50 @@ int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* d, const s3a_s
     S3A_TRY(launch_adjoint(d->dtype, lc, sh, dcd, h->w, grid_for(h, lc, mt), st));
   }
   S3A_TRY(launch_finalize_adjoint(sh, dcd, h->w, st));
+  return S3A_OK;
+}
+
+int s3a_align_pairs_implicit_backward(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* S, const double* gS,
+                                      uint32_t iflags, float* gpx, float* gpy, float* gpz, float* gqx, float* gqy,
+                                      float* gqz, float* gc, double* v_out, int32_t* status_out, s3a_stream stream) {
+  if (!h) return S3A_EINVAL;
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (iflags & ~S3A_IMPLICIT_TANGENT) return S3A_EINVAL;
+  if (d->n_pairs > 0 && (!S || !gS)) return S3A_EINVAL;
+  float* gr[7] = {gpx, gpy, gpz, gqx, gqy, gqz, gc};
+  for (float* p : gr)
+    if (p && !aligned16(p)) return S3A_EINVAL;
+  if (d->n_pairs == 0) return S3A_OK;
+  DeviceGuard g(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
+  const Shape sh = make_shape(d, lc);
+  const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
+  if (mt >= (1ll << 31)) return S3A_EINVAL;
+  rc = ensure_workspace(h, d->n_pairs, mt);
+  if (rc) return rc;
+  if (h->hpart_tiles < mt) {
+    if (h->hpart) {
+      S3A_TRY(hipStreamSynchronize(st));
+      (void)hipFree(h->hpart);
+      h->hpart = nullptr;
+      h->hpart_tiles = 0;
+    }
+    S3A_TRY(hipMalloc(&h->hpart, sizeof(double) * 52 * (size_t)mt));
+    h->hpart_tiles = mt;
+  }
+  CallDesc c = make_call(d);
+  c.S_in = S;
+  c.xi = nullptr;
+  for (int j = 0; j < 7; ++j) c.grad[j] = gr[j];
+  CallDesc* dcd = desc_slot(h);
+  S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
+  S3A_TRY(launch_sched(sh, dcd, h->w, st));
+  S3A_TRY(launch_prep(sh, dcd, h->w, 0, st));
+  TimedLaunch tl(h, st);
+  S3A_TRY(launch_implicit(d->dtype, lc, sh, dcd, h->w, h->hpart, gS, iflags, v_out, status_out, grid_for(h, lc, mt),
+                          st));
   return S3A_OK;
 }
 
