@@ -35,6 +35,7 @@ FP32_B_PER_PT = 28   # px py pz qx qy qz c, 4 B each
 BF16_B_PER_PT = 14
 ADJ_B_PER_PT = 28 + 28  # FP32 planes in, FP32 gradients out
 POINTS_B_PER_PT = 12 + 12  # FP32 xyz in, FP32 world xyz out
+IMPLICIT_B_PER_PT = 28 + 28 + 28  # Hessian pass reads, gradient pass reads and writes
 TOL = (1e-5, 1e-5, 1e-5)
 
 # HBM traffic of the roofline kernel (k_pass, FP32, 256-pair batch) per pass
@@ -301,6 +302,15 @@ def main():
                                    fwd_gbs=FP32_B_PER_PT * N3 / (kf / 1e3) / 1e9, points=N3, pairs=b3.n_pairs)
         log(f"adjoint: fwd {ms_f:.3f} ms (kernel {kf:.3f}), bwd {ms_b:.3f} ms (kernel {kb:.3f}), "
             f"{res['adjoint_fp32']['bwd_gbs']:.0f} GB/s")
+        # implicit derivative of the solved poses: FP64 Hessian pass + per-pair solve + gradient pass
+        gS = torch.from_numpy(np.random.default_rng(6).normal(size=(b3.n_pairs, 7))).to(dev)
+        imp = lambda: h.align_pairs_implicit_backward(pm3, S3, gS, b3.tau, b3.delta, tangent=True)
+        ms_i = timed(imp, args.steps, args.warmup)
+        ki, _ = kernel_ms(imp, args.steps)
+        res["implicit_fp32"] = dict(ms=ms_i, kernel_ms=ki, points=N3,
+                                    gbs=IMPLICIT_B_PER_PT * N3 / (ki / 1e3) / 1e9,
+                                    frac=IMPLICIT_B_PER_PT * N3 / (ki / 1e3) / 1e9 / HBM_PEAK_GBS)
+        log(f"implicit backward: {ms_i:.3f} ms (kernels {ki:.3f}, {res['implicit_fp32']['gbs']:.0f} GB/s)")
         del pm3
 
     # ---- pose-graph solve: 1000 nodes, 999 sequential + 200 loop edges
