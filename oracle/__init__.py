@@ -18,6 +18,8 @@ cost     : Huber-weighted alignment cost, its analytic gradient, and central
 implicit : derivative of the solved pose with respect to the points and
            confidences (implicit function theorem, exact Huber Hessian)
 pgo      : dense Gauss-Newton Sim(3) pose-graph solve (Sec. III-E)
+depth    : points of a depth-map pair (unprojection with each submap's camera,
+           Sec. III-C.1)
 points   : point correction: submap points to the world frame, sparse-map
            replacement (Sec. III-C.3)
 metrics  : pose-error measures used to compare two Sim(3) estimates
