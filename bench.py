@@ -35,6 +35,7 @@ FP32_B_PER_PT = 28   # px py pz qx qy qz c, 4 B each
 BF16_B_PER_PT = 14
 ADJ_B_PER_PT = 28 + 28  # FP32 planes in, FP32 gradients out
 POINTS_B_PER_PT = 12 + 12  # FP32 xyz in, FP32 world xyz out
+DEPTH_B_PER_PX = 12  # FP32 d_p, d_q, c per pixel
 IMPLICIT_B_PER_PT = 28 + 28 + 28  # Hessian pass reads, gradient pass reads and writes
 TOL = (1e-5, 1e-5, 1e-5)
 
@@ -74,7 +75,12 @@ def _verify_pair(args):
     from threadpoolctl import threadpool_limits
     from oracle import irls, metrics
     b = _BATCHES[name]
-    p, q, c = b.decoded_pair(k)
+    if hasattr(b, "pairs"):  # depth-map input: the oracle unprojects first
+        from oracle import depth
+        dp, dq, c = b.decoded(k)
+        p, q = depth.unproject_pair(dp, dq, b.pairs[k])
+    else:
+        p, q, c = b.decoded_pair(k)
     with threadpool_limits(1):
         t0 = time.perf_counter()
         ref = irls.irls_align(p, q, c, b.tau, b.delta, b.iters)
@@ -94,7 +100,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="fewer pairs verified, no plain/config-1 leg")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="bf16,plain,adjoint,pgo,points", help="comma list of extra legs")
+    ap.add_argument("--legs", default="bf16,depth,plain,adjoint,pgo,points", help="comma list of extra legs")
     ap.add_argument("--verify", default="all", choices=["all", "sample", "none"])
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--tuning", default="", help="force the launch shape wg,items,occupancy (skips autotuning)")
@@ -118,6 +124,9 @@ def main():
         _BATCHES["cfg1"] = synth.config1()
     if "adjoint" in legs:
         _BATCHES["cfg3"] = synth.config3()
+    if "depth" in legs:
+        from synth import depthmaps
+        _BATCHES["depth"] = depthmaps.config_depth()
     log(f"generated inputs in {time.perf_counter() - t0:.1f}s: cfg2 {b2.n_pairs} pairs {b2.n_points} points")
     pool = mp.get_context("fork").Pool(args.workers) if args.verify != "none" else None
 
@@ -252,6 +261,26 @@ def main():
                                           batched_speedup=value / (V1 / (ms1 / 1e3)))
             log(f"plain fp32 cfg1: {ms1:.2f} ms/step, {V1 / (ms1 / 1e3) / 1e9:.3f} Gpts/s; verify {ver1}")
             del pm1
+
+    # ---- depth-map input: the same alignment with points unprojected inside the pass kernels
+    if "depth" in legs:
+        bd = _BATCHES["depth"]
+        dm = s3a.DepthPointmaps.from_batch(bd, dev)
+        Sd = torch.empty((bd.n_pairs, 16), dtype=torch.float64, device=dev)
+        stepd = lambda: h.align_depth_pairs(dm, bd.tau, bd.delta, bd.iters, out=Sd, info=False)
+        ms_d = timed(stepd, args.steps, args.warmup)
+        kd, kn = kernel_ms(stepd, args.steps)
+        Sd, ibd = h.align_depth_pairs(dm, bd.tau, bd.delta, bd.iters)
+        torch.cuda.synchronize()
+        infod = s3a.info_to_numpy(ibd)
+        Vd = int(infod["n_valid"].sum())
+        verd = verify("depth", Sd, ibd, 16 if args.verify != "none" else 1)
+        gbs_d = DEPTH_B_PER_PX * bd.n_points / (kd / kn / 1e3) / 1e9
+        res["depth_fp32"] = dict(ms_per_step=ms_d, points_per_s=Vd / (ms_d / 1e3), pixels=bd.n_points, valid_points=Vd,
+                                 kernel_ms=kd, pass_gbs=gbs_d, pass_frac=gbs_d / HBM_PEAK_GBS, verify=verd)
+        log(f"depth fp32: {ms_d:.3f} ms/step, {Vd / (ms_d / 1e3) / 1e9:.2f} G valid pts/s over {bd.n_points} pixels, "
+            f"pass {gbs_d:.0f} GB/s; verify {verd}")
+        del dm
 
     # ---- point correction: the batch's source points to the world frame, then a sparse-map replacement
     if "points" in legs:

@@ -29,6 +29,16 @@ class AlignDesc(ctypes.Structure):
                 ("huber_delta", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
 
 
+class DepthDesc(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("n_pairs", ctypes.c_int32), ("n_points", ctypes.c_int64),
+                ("offsets", c_void_p), ("depth_p", c_void_p), ("depth_q", c_void_p), ("conf", c_void_p),
+                ("pairs", c_void_p), ("conf_threshold", ctypes.c_float), ("irls_iters", ctypes.c_int32),
+                ("huber_delta", ctypes.c_double), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32)]
+
+
+DEPTH_PAIR_BYTES = 528  # s3a_depth_pair
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("wg", ctypes.c_int32), ("items", ctypes.c_int32), ("occupancy", ctypes.c_int32),
                 ("window", ctypes.c_int32)]
@@ -73,6 +83,8 @@ _EXPORTS = {
                                           c_void_p]),
     "s3a_align_pairs_implicit_backward": (ctypes.c_int, [c_void_p, ctypes.POINTER(AlignDesc), c_void_p, c_void_p,
                                                          ctypes.c_uint32] + [c_void_p] * 9 + [c_void_p]),
+    "s3a_align_depth_pairs": (ctypes.c_int, [c_void_p, ctypes.POINTER(DepthDesc), c_void_p, c_void_p, c_void_p,
+                                             c_void_p]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -168,6 +180,53 @@ class Pointmaps:
         return d
 
 
+class DepthPointmaps:
+    """Depth-map input: three device planes (source depth, target depth,
+    confidence; FP32, or BF16 bit patterns), int64 offsets, and the per-pair
+    camera table (n_pairs x 528 bytes, s3a_depth_pair layout) on the device."""
+
+    def __init__(self, planes, offsets, pairs, dtype):
+        assert len(planes) == 3
+        self.planes = list(planes)
+        self.offsets = offsets
+        self.pairs = pairs
+        self.dtype = dtype
+        self.n_points = int(planes[0].numel())
+        self.n_pairs = int(offsets.numel()) - 1
+        self.device = planes[0].device
+        for p in planes:
+            assert p.is_contiguous() and p.numel() == self.n_points and p.device == self.device
+        assert pairs.numel() == DEPTH_PAIR_BYTES * self.n_pairs
+
+    @staticmethod
+    def from_batch(batch, device="cuda"):
+        """synth.depthmaps.DepthBatch -> device DepthPointmaps (planes padded so
+        that each starts 16-byte aligned)."""
+        if batch.dtype == "bf16":
+            planes = [torch.from_numpy(np.ascontiguousarray(x).view(np.int16)).to(device) for x in (batch.dp, batch.dq, batch.c)]
+            dt = BF16
+        else:
+            planes = [torch.from_numpy(np.ascontiguousarray(x)).to(device) for x in (batch.dp, batch.dq, batch.c)]
+            dt = F32
+        pairs = torch.from_numpy(np.ascontiguousarray(batch.pairs).view(np.uint8).copy()).to(device)
+        return DepthPointmaps(planes, torch.from_numpy(batch.offsets).to(device), pairs, dt)
+
+    def desc(self, tau, delta, iters, flags=0):
+        d = DepthDesc()
+        d.dtype = self.dtype
+        d.n_pairs = self.n_pairs
+        d.n_points = self.n_points
+        d.offsets = self.offsets.data_ptr()
+        d.depth_p, d.depth_q, d.conf = (t.data_ptr() for t in self.planes)
+        d.pairs = self.pairs.data_ptr()
+        d.conf_threshold = float(tau)
+        d.irls_iters = int(iters)
+        d.huber_delta = float(delta)
+        d.flags = int(flags)
+        d.reserved = 0
+        return d
+
+
 class Handle:
     def __init__(self, device=0):
         self.lib = load_library()
@@ -195,6 +254,16 @@ class Handle:
         d = pm.desc(tau, delta, iters, flags)
         _check(self.lib.s3a_align_pairs(self.h, ctypes.byref(d), _ptr(init), _ptr(S), _ptr(ib),
                                         _stream(pm.device)), self.h)
+        return S, ib
+
+    def align_depth_pairs(self, dm, tau, delta=0.05, iters=10, init=None, flags=0, info=True, out=None):
+        """Alignment of depth-map pairs (DepthPointmaps). Returns (S, info) as align_pairs."""
+        n = dm.n_pairs
+        S = out if out is not None else torch.empty((n, SIM3_DOUBLES), dtype=torch.float64, device=dm.device)
+        ib = torch.empty((n, INFO_DTYPE.itemsize), dtype=torch.uint8, device=dm.device) if info else None
+        d = dm.desc(tau, delta, iters, flags)
+        _check(self.lib.s3a_align_depth_pairs(self.h, ctypes.byref(d), _ptr(init), _ptr(S), _ptr(ib),
+                                              _stream(dm.device)), self.h)
         return S, ib
 
     def align_cost(self, pm, S, xi, tau, delta=0.05):

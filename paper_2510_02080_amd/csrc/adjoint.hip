@@ -32,7 +32,7 @@ __global__ __launch_bounds__(WG) void k_adjoint(Shape sh, const CallDesc* __rest
       const int64_t g0 = td.begin + (int64_t)(it * WG + (int)threadIdx.x) * VEC;
       if (g0 >= td.end) continue;
       float v[7][VEC];
-      Planes<DT>::load(pl, g0, sh.n_points, v);
+      Planes<DT>::load(SrcCtx<DT>{pl}, g0, sh.n_points, v);
       float go[7][VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {

@@ -95,7 +95,8 @@ __global__ __launch_bounds__(WG) void k_pass(Shape sh, const CallDesc* __restric
   for (int t = tile_lo + (int)blockIdx.x; t < total; t += (int)gridDim.x) {
     const TileDesc td = load_tile(w.tiles + t);
     const PointParams P = load_params(w.params + td.pair);
-    tile_body<DT, MODE, WG, ITEMS>(sh, pl, td, P, red, w.partials + (int64_t)t * NSTAT);
+    const SrcCtx<DT> src = make_src<DT>(pl, w, td);
+    tile_body<DT, MODE, WG, ITEMS>(sh, src, td, P, red, w.partials + (int64_t)t * NSTAT);
   }
 }
 
@@ -166,6 +167,16 @@ static hipError_t launch_pass_t(const LaunchCfg& lc, const Shape& sh, const Call
 
 hipError_t launch_pass(int dtype, int mode, const LaunchCfg& lc, const Shape& sh, const CallDesc* cd,
                        const Work& w, int32_t tile_lo, int32_t tile_hi, int grid, hipStream_t st) {
+  if (dtype == DT_DEPTH_F32) {
+    if (mode == MODE_MOMENTS) return launch_pass_t<DT_DEPTH_F32, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN) return launch_pass_t<DT_DEPTH_F32, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    return hipErrorInvalidValue;
+  }
+  if (dtype == DT_DEPTH_BF16) {
+    if (mode == MODE_MOMENTS) return launch_pass_t<DT_DEPTH_BF16, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN) return launch_pass_t<DT_DEPTH_BF16, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    return hipErrorInvalidValue;
+  }
   if (dtype == S3A_F32) {
     if (mode == MODE_MOMENTS) return launch_pass_t<S3A_F32, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_GN) return launch_pass_t<S3A_F32, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
@@ -196,6 +207,54 @@ hipError_t launch_finalize(int kind, const Shape& sh, const CallDesc* cd, const 
 hipError_t launch_prep(const Shape& sh, const CallDesc* cd, const Work& w, int adjoint, hipStream_t st) {
   if (sh.n_pairs == 0) return hipSuccess;
   hipLaunchKernelGGL(k_prep, dim3((sh.n_pairs + 127) / 128), dim3(128), 0, st, sh, cd, w, adjoint);
+  return hipGetLastError();
+}
+
+// Depth input: the caller's cameras in pass form (reciprocal focal lengths,
+// offsets), geometry checked and sanitised; a pair with invalid geometry, or
+// with more elements than its frames hold, is marked bad (BADRANGE).
+__global__ void k_depth_prep(Shape sh, const CallDesc* __restrict__ cd, Work w) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= sh.n_pairs) return;
+  const s3a_depth_pair& src = cd->depth[k];
+  int W = src.width, HW = src.frame_pixels, nf = src.n_frames;
+  bool ok = W >= 1 && HW >= W && HW % W == 0 && nf >= 1 && nf <= DEPTH_MAX_FRAMES && src.reserved == 0;
+  const PairSched sc = w.sched[k];
+  if (ok && !sc.bad) ok = sc.b - sc.a <= (int64_t)nf * HW;
+  if (!ok) {
+    W = 1;
+    HW = 1;
+    nf = 1;
+  }
+  DepthPair dp;
+  dp.width = W;
+  dp.rows = HW / W;
+  dp.frame_pixels = HW;
+  dp.n_frames = nf;
+  dp.inv_width = 1.0f / (float)W;
+  dp.inv_frame = 1.0f / (float)HW;
+  dp.pad[0] = dp.pad[1] = 0;
+  for (int f = 0; f < DEPTH_MAX_FRAMES; ++f) {
+    const s3a_camera* in[2] = {src.p + f, src.q + f};
+    DepthCam* out[2] = {dp.p + f, dp.q + f};
+    for (int side = 0; side < 2; ++side) {
+      const s3a_camera& c = *in[side];
+      DepthCam& o = *out[side];
+      o.ifx = 1.0f / c.fx;
+      o.ify = 1.0f / c.fy;
+      o.ox = -c.cx / c.fx;
+      o.oy = -c.cy / c.fy;
+      for (int i = 0; i < 9; ++i) o.R[i] = c.R[i];
+      for (int i = 0; i < 3; ++i) o.t[i] = c.t[i];
+    }
+  }
+  w.dpairs[k] = dp;
+  if (!ok) w.sched[k].bad = 1;
+}
+
+hipError_t launch_depth_prep(const Shape& sh, const CallDesc* cd, const Work& w, hipStream_t st) {
+  if (sh.n_pairs == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_depth_prep, dim3((sh.n_pairs + 63) / 64), dim3(64), 0, st, sh, cd, w);
   return hipGetLastError();
 }
 

@@ -34,10 +34,31 @@ struct Planes;
 typedef float s3a_f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int s3a_u4 __attribute__((ext_vector_type(4)));
 
+// What a tile's loads need besides the element index: the stored xyz planes,
+// or for depth input the three planes and the tile's pair (start element and
+// cameras, in uniform registers when the whole tile lies in one frame).
+template <int DT>
+struct SrcCtx {
+  const void* const* pl;
+};
+
+struct DepthCtx {
+  const void* pl[3];
+  const DepthPair* dp;
+  int64_t a;        // first element of the pair
+  int frame;        // the tile's frame when it lies in one, else -1
+  DepthCam cp, cq;  // that frame's cameras (valid when frame >= 0)
+};
+template <>
+struct SrcCtx<DT_DEPTH_F32> : DepthCtx {};
+template <>
+struct SrcCtx<DT_DEPTH_BF16> : DepthCtx {};
+
 template <>
 struct Planes<S3A_F32> {
   static constexpr int VEC = 4;
-  __device__ static inline void load(const void* const* pl, int64_t g0, int64_t n, float (&v)[7][4]) {
+  __device__ static inline void load(const SrcCtx<S3A_F32>& src, int64_t g0, int64_t n, float (&v)[7][4]) {
+    const void* const* pl = src.pl;
     if (g0 + 4 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
@@ -59,7 +80,8 @@ struct Planes<S3A_BF16> {
   static constexpr int VEC = 8;
   __device__ static inline float lo(uint32_t u) { return __uint_as_float(u << 16); }
   __device__ static inline float hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
-  __device__ static inline void load(const void* const* pl, int64_t g0, int64_t n, float (&v)[7][8]) {
+  __device__ static inline void load(const SrcCtx<S3A_BF16>& src, int64_t g0, int64_t n, float (&v)[7][8]) {
+    const void* const* pl = src.pl;
     if (g0 + 8 <= n) {
 #pragma unroll
       for (int j = 0; j < 7; ++j) {
@@ -143,6 +165,136 @@ __device__ inline TileDesc load_tile(const TileDesc* p) {
   r.pair = uniform_i32(p->pair);
   r.pad = 0;
   return r;
+}
+
+// Depth input: three planes (d_p, d_q, c), the pixel's frame, row and column
+// from its index in the pair, and each side unprojected with its camera:
+// x = R (d ((col, row) * inv_f + o, 1)) + t. Elements before the pair's start
+// (the head of a boundary vector) get the pair's first pixel; the tile bodies
+// zero them anyway.
+__device__ inline DepthCam load_cam_uniform(const DepthCam* c) {
+  DepthCam r;
+  r.ifx = uniform_f32(c->ifx);
+  r.ify = uniform_f32(c->ify);
+  r.ox = uniform_f32(c->ox);
+  r.oy = uniform_f32(c->oy);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) r.R[i] = uniform_f32(c->R[i]);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) r.t[i] = uniform_f32(c->t[i]);
+  return r;
+}
+
+__device__ inline void unproject(const DepthCam& c, float col, float row, float d, float* x) {
+  const float rx = fmaf(col, c.ifx, c.ox), ry = fmaf(row, c.ify, c.oy);
+#pragma unroll
+  for (int i = 0; i < 3; ++i) x[i] = fmaf(d, fmaf(c.R[3 * i], rx, fmaf(c.R[3 * i + 1], ry, c.R[3 * i + 2])), c.t[i]);
+}
+
+// q = floor(x / m) for 0 <= x < 2^31, m >= 1: a float estimate, corrected.
+__device__ inline int div_floor(int x, int m, float inv_m) {
+  int q = (int)((float)x * inv_m);
+  q -= (q * m > x) ? 1 : 0;
+  q += ((q + 1) * m <= x) ? 1 : 0;
+  q -= (q * m > x) ? 1 : 0;
+  return q;
+}
+
+template <int DT>
+struct DepthPlanes {
+  static constexpr bool BF = DT == DT_DEPTH_BF16;
+  static constexpr int VEC = BF ? 8 : 4;
+  __device__ static inline void load(const SrcCtx<DT>& s, int64_t g0, int64_t n, float (&v)[7][VEC]) {
+    float d[3][VEC];
+    if (g0 + VEC <= n) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if constexpr (BF) {
+          const s3a_u4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(s.pl[j]) + g0));
+          d[j][0] = __uint_as_float(x.x << 16); d[j][1] = __uint_as_float(x.x & 0xffff0000u);
+          d[j][2] = __uint_as_float(x.y << 16); d[j][3] = __uint_as_float(x.y & 0xffff0000u);
+          d[j][4] = __uint_as_float(x.z << 16); d[j][5] = __uint_as_float(x.z & 0xffff0000u);
+          d[j][6] = __uint_as_float(x.w << 16); d[j][7] = __uint_as_float(x.w & 0xffff0000u);
+        } else {
+          const s3a_f4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_f4*)(static_cast<const float*>(s.pl[j]) + g0));
+          d[j][0] = x.x; d[j][1] = x.y; d[j][2] = x.z; d[j][3] = x.w;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          if constexpr (BF)
+            d[j][e] = (g0 + e < n) ? __uint_as_float((uint32_t)static_cast<const uint16_t*>(s.pl[j])[g0 + e] << 16) : 0.0f;
+          else
+            d[j][e] = (g0 + e < n) ? static_cast<const float*>(s.pl[j])[g0 + e] : 0.0f;
+        }
+    }
+    const DepthPair* P = s.dp;
+    const int W = P->width, H = P->rows, HW = P->frame_pixels, nf = P->n_frames;
+    int j = (int)(g0 - s.a);
+    j = j < 0 ? 0 : j;
+    int f = div_floor(j, HW, P->inv_frame);
+    const int pin = j - f * HW;
+    int row = div_floor(pin, W, P->inv_width);
+    int col = pin - row * W;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      float x[3], y[3];
+      if (s.frame >= 0) {
+        unproject(s.cp, (float)col, (float)row, d[0][e], x);
+        unproject(s.cq, (float)col, (float)row, d[1][e], y);
+      } else {
+        const int fc = f < nf ? f : nf - 1;
+        unproject(P->p[fc], (float)col, (float)row, d[0][e], x);
+        unproject(P->q[fc], (float)col, (float)row, d[1][e], y);
+      }
+      v[0][e] = x[0]; v[1][e] = x[1]; v[2][e] = x[2];
+      v[3][e] = y[0]; v[4][e] = y[1]; v[5][e] = y[2];
+      v[6][e] = d[2][e];
+      if (g0 + e >= s.a) {  // advance to the next pixel
+        if (++col == W) {
+          col = 0;
+          if (++row == H) {
+            row = 0;
+            ++f;
+          }
+        }
+      }
+    }
+  }
+};
+
+template <>
+struct Planes<DT_DEPTH_F32> : DepthPlanes<DT_DEPTH_F32> {};
+template <>
+struct Planes<DT_DEPTH_BF16> : DepthPlanes<DT_DEPTH_BF16> {};
+
+// The load context of a tile (see SrcCtx).
+template <int DT>
+__device__ inline SrcCtx<DT> make_src(const void* const* pl, const Work& w, const TileDesc& td) {
+  if constexpr (DT == DT_DEPTH_F32 || DT == DT_DEPTH_BF16) {
+    SrcCtx<DT> s;
+    s.pl[0] = pl[0];
+    s.pl[1] = pl[1];
+    s.pl[2] = pl[2];
+    s.dp = w.dpairs + td.pair;
+    s.a = td.lo;
+    const int HW = uniform_i32(s.dp->frame_pixels), nf = uniform_i32(s.dp->n_frames);
+    const int64_t first = td.begin > td.lo ? td.begin : td.lo;
+    const int f0 = (int)((first - td.lo) / HW), f1 = (int)((td.end - 1 - td.lo) / HW);
+    s.frame = (f0 == f1 && f0 < nf && td.end > first) ? f0 : -1;
+    if (s.frame >= 0) {
+      s.cp = load_cam_uniform(s.dp->p + s.frame);
+      s.cq = load_cam_uniform(s.dp->q + s.frame);
+    }
+    return s;
+  } else {
+    (void)w;
+    (void)td;
+    return SrcCtx<DT>{pl};
+  }
 }
 
 // ---------------------------------------------------------------- per-point terms
@@ -305,7 +457,7 @@ __device__ inline void block_store_f64(double (&acc)[N], double (*red)[NSTAT], d
 // confidence threshold, or (in pairs that hold any) with a NaN/Inf value get
 // zero weight and zeroed coordinates.
 template <int DT, int WG, int ITEMS>
-__device__ inline void tile_gn(const Shape& sh, const void* const* pl, const TileDesc& td, const PointParams& P,
+__device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td, const PointParams& P,
                                double (*red)[NSTAT], double* out) {
   constexpr int VEC = Planes<DT>::VEC;
   float a[NSTAT];
@@ -379,7 +531,7 @@ __device__ inline void tile_gn(const Shape& sh, const void* const* pl, const Til
 // coordinates are uncentred here, so the second moments must keep more than
 // FP32 precision), integer counts, DPP wavefront reduction.
 template <int DT, int WG, int ITEMS>
-__device__ inline void tile_moments(const Shape& sh, const void* const* pl, const TileDesc& td,
+__device__ inline void tile_moments(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td,
                                    double (*red)[NSTAT], double* out) {
   constexpr int VEC = Planes<DT>::VEC;
   double a[NSTAT];
@@ -426,7 +578,7 @@ __device__ inline void tile_moments(const Shape& sh, const void* const* pl, cons
 
 // Cost pass over one tile: sum w, sum w rho (FP64 residuals, FP64 sums), V.
 template <int DT, int WG, int ITEMS>
-__device__ inline void tile_cost(const Shape& sh, const void* const* pl, const TileDesc& td, const PointParams& P,
+__device__ inline void tile_cost(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td, const PointParams& P,
                                  double (*red)[NSTAT], double* out) {
   constexpr int VEC = Planes<DT>::VEC;
   double acc[3] = {0.0, 0.0, 0.0};
@@ -452,7 +604,7 @@ __device__ inline void tile_cost(const Shape& sh, const void* const* pl, const T
 }
 
 template <int DT, int MODE, int WG, int ITEMS>
-__device__ inline void tile_body(const Shape& sh, const void* const* pl, const TileDesc& td,
+__device__ inline void tile_body(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td,
                                  const PointParams& P, double (*red)[NSTAT], double* out) {
   if constexpr (MODE == MODE_GN) {
     tile_gn<DT, WG, ITEMS>(sh, pl, td, P, red, out);

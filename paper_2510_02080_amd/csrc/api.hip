@@ -132,6 +132,7 @@ int ensure_workspace(s3a_handle* h, int n_pairs, int64_t tiles) {
   const size_t o_flag = off;  off = align_up(off + sizeof(uint32_t) * (np + 64));
   const size_t o_tot = off;   off = align_up(off + sizeof(int32_t) * 64);
   const size_t o_desc = off;  off = align_up(off + sizeof(CallDesc));
+  const size_t o_dpair = off; off = align_up(off + sizeof(DepthPair) * np);
   clear_graphs(h);
   if (h->ws) {
     (void)hipDeviceSynchronize();
@@ -158,6 +159,7 @@ int ensure_workspace(s3a_handle* h, int n_pairs, int64_t tiles) {
   h->w.total_tiles = reinterpret_cast<int32_t*>(b + o_tot);
   h->w.scan_tmp = nullptr;
   h->desc = reinterpret_cast<CallDesc*>(b + o_desc);
+  h->w.dpairs = reinterpret_cast<DepthPair*>(b + o_dpair);
   h->cap_pairs = np;
   h->cap_tiles = nt;
   return S3A_OK;
@@ -194,13 +196,14 @@ int size_class(int64_t n_points) {
 LaunchCfg default_cfg(int dtype) {
   LaunchCfg c;
   c.wg = 256;
-  c.items = dtype == S3A_BF16 ? 2 : 4;
+  c.items = (dtype & 1) ? 2 : 4;
   c.occupancy = 4;
   c.window = 0;
   return c;
 }
 
 LaunchCfg pick_cfg(s3a_handle* h, int dtype, int64_t n_points) {
+  dtype &= 1;  // depth inputs use the launch shape of their plane type
   if (h->forced[dtype]) return h->forced_cfg[dtype];
   const int sc = size_class(n_points);
   for (auto& t : h->tuned)
@@ -255,6 +258,10 @@ hipError_t enqueue_batched_multi(s3a_handle* h, int dtype, const LaunchCfg& lc, 
                                  hipStream_t st) {
   hipError_t e = launch_sched(sh, dcd, h->w, st);
   if (e != hipSuccess) return e;
+  if (dtype == DT_DEPTH_F32 || dtype == DT_DEPTH_BF16) {
+    e = launch_depth_prep(sh, dcd, h->w, st);
+    if (e != hipSuccess) return e;
+  }
   const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
   const int grid = grid_for(h, lc, mt);
   const int npass = 1 + sh.K + ((sh.flags & S3A_FLAG_FINAL_COST) ? 1 : 0);
@@ -348,13 +355,16 @@ int s3a_destroy(s3a_handle* h) {
   return S3A_OK;
 }
 
-int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init, s3a_sim3* S_out,
-                    s3a_align_info* info, s3a_stream stream) {
-  if (!h) return S3A_EINVAL;
-  int rc = check_desc(d);
-  if (rc) return rc;
-  if (d->n_pairs > 0 && !S_out) return S3A_EINVAL;
-  if (d->n_pairs == 0) return S3A_OK;
+}  // extern "C"
+
+namespace {
+
+// The alignment driver of s3a_align_pairs and s3a_align_depth_pairs: d holds
+// a checked descriptor whose dtype may be an internal depth type (planes px,
+// py, pz = d_p, d_q, c), with the caller's cameras in depth.
+int align_run(s3a_handle* h, const s3a_align_desc* d, const s3a_depth_pair* depth, const s3a_sim3* init,
+              s3a_sim3* S_out, s3a_align_info* info, s3a_stream stream) {
+  int rc = S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
   const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
@@ -367,12 +377,14 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
   c.init = init;
   c.S_out = S_out;
   c.info = info;
+  c.depth = depth;
   CallDesc* dcd = desc_slot(h);
 
   if (d->flags & S3A_FLAG_PLAIN) {
     // one pair at a time: read the schedule back, then 1 + K (+1) passes per pair
     S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
     S3A_TRY(launch_sched(sh, dcd, h->w, st));
+    if (depth) S3A_TRY(launch_depth_prep(sh, dcd, h->w, st));
     std::vector<PairSched> sched(d->n_pairs);
     S3A_TRY(hipMemcpyAsync(sched.data(), h->w.sched, sizeof(PairSched) * d->n_pairs, hipMemcpyDeviceToHost, st));
     S3A_TRY(hipStreamSynchronize(st));
@@ -447,6 +459,48 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
   S3A_TRY(hipMemcpyAsync(dcd, &c, sizeof(c), hipMemcpyHostToDevice, st));
   S3A_TRY(hipGraphLaunch(exec, st));
   return S3A_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init, s3a_sim3* S_out,
+                    s3a_align_info* info, s3a_stream stream) {
+  if (!h) return S3A_EINVAL;
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->n_pairs > 0 && !S_out) return S3A_EINVAL;
+  if (d->n_pairs == 0) return S3A_OK;
+  return align_run(h, d, nullptr, init, S_out, info, stream);
+}
+
+int s3a_align_depth_pairs(s3a_handle* h, const s3a_depth_desc* dd, const s3a_sim3* init, s3a_sim3* S_out,
+                          s3a_align_info* info, s3a_stream stream) {
+  if (!h || !dd) return S3A_EINVAL;
+  if (dd->dtype != S3A_F32 && dd->dtype != S3A_BF16) return S3A_EINVAL;
+  if (dd->flags & S3A_FLAG_PERSISTENT) return S3A_EINVAL;
+  if (dd->n_pairs > 0 && (!S_out || !dd->pairs)) return S3A_EINVAL;
+  s3a_align_desc d;
+  memset(&d, 0, sizeof(d));
+  d.dtype = dd->dtype == S3A_F32 ? DT_DEPTH_F32 : DT_DEPTH_BF16;
+  d.n_pairs = dd->n_pairs;
+  d.n_points = dd->n_points;
+  d.offsets = dd->offsets;
+  // the three depth-input planes; the check below wants seven non-null planes
+  d.px = dd->depth_p; d.py = dd->depth_q; d.pz = dd->conf;
+  d.qx = dd->depth_p; d.qy = dd->depth_q; d.qz = dd->conf; d.conf = dd->conf;
+  d.conf_threshold = dd->conf_threshold;
+  d.irls_iters = dd->irls_iters;
+  d.huber_delta = dd->huber_delta;
+  d.flags = dd->flags;
+  d.reserved = dd->reserved;
+  s3a_align_desc chk = d;
+  chk.dtype = dd->dtype;
+  const int rc = check_desc(&chk);
+  if (rc) return rc;
+  if (d.n_pairs == 0) return S3A_OK;
+  return align_run(h, &d, dd->pairs, init, S_out, info, stream);
 }
 
 int s3a_align_cost(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* S, const double* xi, double* L_out,

@@ -59,7 +59,7 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
       const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
       if (rel0 >= end_rel) break;
       float v[7][VEC];
-      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+      Planes<DT>::load(SrcCtx<DT>{pl}, td.begin + rel0, sh.n_points, v);
 #pragma unroll 1
       for (int e = 0; e < VEC; ++e) {
         float x[7];
@@ -258,7 +258,7 @@ __global__ __launch_bounds__(WG) void k_igrad(Shape sh, const CallDesc* __restri
       const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
       if (rel0 >= end_rel) break;
       float v[7][VEC];
-      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+      Planes<DT>::load(SrcCtx<DT>{pl}, td.begin + rel0, sh.n_points, v);
       float go[7][VEC];
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {

@@ -27,6 +27,30 @@ enum PassMode { MODE_MOMENTS = 0, MODE_GN = 1, MODE_COST = 2, MODE_ADJOINT = 3 }
 // FP32 (4 elements) and BF16 (8 elements) planes are aligned.
 constexpr int64_t TILE_ALIGN = 8;
 
+// Internal source types of the point passes: stored xyz (the public S3A_F32,
+// S3A_BF16) or depth maps unprojected on the fly (Sec. III-C.1, submaps from
+// depth and camera parameters), FP32 or BF16 planes.
+constexpr int DT_DEPTH_F32 = 2;
+constexpr int DT_DEPTH_BF16 = 3;
+constexpr int DEPTH_MAX_FRAMES = 4;
+
+// A camera as the point passes use it: x_submap = R (d ((u, v) * inv_f + o, 1)) + t.
+struct DepthCam {
+  float ifx, ify, ox, oy;  // 1/fx, 1/fy, -cx/fx, -cy/fy
+  float R[9];
+  float t[3];
+};
+
+// Per pair: frame geometry (sanitised: width, rows >= 1) and the two submaps'
+// cameras of each shared frame.
+struct DepthPair {
+  int32_t width, rows, frame_pixels, n_frames;
+  float inv_width, inv_frame;  // 1/width, 1/frame_pixels (division estimates, corrected exactly)
+  int32_t pad[2];
+  DepthCam p[DEPTH_MAX_FRAMES];
+  DepthCam q[DEPTH_MAX_FRAMES];
+};
+
 struct TileDesc {
   int64_t begin;  // first element loaded (multiple of TILE_ALIGN)
   int64_t end;    // one past the last element of this tile
@@ -90,6 +114,7 @@ struct CallDesc {
   double* C_out;
   float* grad[7];
   double* gxi;
+  const s3a_depth_pair* depth;  // caller's per-pair cameras (depth input), or null
 };
 
 // Shape of a call (passed by value).
@@ -115,6 +140,7 @@ struct Work {
   uint32_t* counters;  // [n_pairs] arrivals, then 4 scheduling words
   uint32_t* flags;     // [n_pairs] per-pair published pass (persistent launch)
   int32_t* scan_tmp;
+  DepthPair* dpairs;   // [n_pairs] cameras in pass form (depth input)
 };
 
 }  // namespace s3a

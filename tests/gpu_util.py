@@ -59,7 +59,7 @@ def srt_of(T):
     return s, T[:3, :3] / s, T[:3, 3]
 
 
-def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where=""):
+def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where="", dr=DR):
     """Compare one pair's GPU result with the oracle's (status, pose, counts,
     weight sum, cost, inliers, H, g)."""
     assert int(info["status"]) == ref["status"], f"{where}: status {info['status']} vs {ref['status']}"
@@ -75,7 +75,7 @@ def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where=""):
     K = len(ref["costs"])
     if K:
         L = ref["costs"][-1]
-        assert abs(info["cost"] - L) <= 1e-5 * abs(L) + np.sqrt(2 * abs(L)) * DR, where
+        assert abs(info["cost"] - L) <= 1e-5 * abs(L) + np.sqrt(2 * abs(L)) * dr, where
         assert abs(int(info["n_inliers"]) - ref["inliers"][-1]) <= max(3, 1e-4 * ref["V"]), where
         Hr = ref["H"] / 1.0
         Hu = Hr[np.triu_indices(7)]

@@ -47,6 +47,7 @@ int main(void) {
          sizeof(s3a_pgo_params), sizeof(s3a_pgo_report), sizeof(s3a_tuning));
   printf("%zu %zu %zu %zu %zu\n", offsetof(s3a_align_desc, conf_threshold), offsetof(s3a_align_desc, huber_delta),
          offsetof(s3a_align_info, n_valid), offsetof(s3a_align_info, status), offsetof(s3a_pgo_report, status));
+  printf("%zu %zu %zu\n", sizeof(s3a_depth_desc), sizeof(s3a_depth_pair), sizeof(s3a_camera));
   return 0;
 }
 ''')
@@ -65,6 +66,10 @@ int main(void) {
     assert sizes[8] == b.INFO_DTYPE.fields["n_valid"][1]
     assert sizes[9] == b.INFO_DTYPE.fields["status"][1]
     assert sizes[10] == b.PgoReport.status.offset
+    from synth import depthmaps
+    assert sizes[11] == ctypes.sizeof(b.DepthDesc)
+    assert sizes[12] == b.DEPTH_PAIR_BYTES == depthmaps.PAIR_DTYPE.itemsize
+    assert sizes[13] == depthmaps.CAM_DTYPE.itemsize
 
 
 def test_host_argument_checks(lib):
@@ -81,6 +86,7 @@ def test_host_argument_checks(lib):
     assert L.s3a_create(None, 0) == b.EINVAL
     assert L.s3a_destroy(None) == b.EINVAL
     assert L.s3a_set_tuning(None, 0, None) == b.EINVAL
+    assert L.s3a_align_depth_pairs(None, None, None, None, None, None) == b.EINVAL
     assert L.s3a_align_pairs_implicit_backward(None, ctypes.byref(d), None, None, 0, *([None] * 9), None) == b.EINVAL
     assert L.s3a_transform_points(None, 0, 0, 0, None, *([None] * 8), None) == b.EINVAL
     assert L.s3a_correct_points(None, 0, None, None, 0, None, None, None, 0, None, None, None, None, None) == b.EINVAL
