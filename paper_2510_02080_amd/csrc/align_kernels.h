@@ -45,9 +45,11 @@ struct SrcCtx {
 struct DepthCtx {
   const void* pl[3];
   const DepthPair* dp;
-  int64_t a;        // first element of the pair
-  int frame;        // the tile's frame when it lies in one, else -1
-  DepthCam cp, cq;  // that frame's cameras (valid when frame >= 0)
+  int64_t a;            // first element of the pair
+  int width, rows, frame_pixels, n_frames;
+  float inv_width, inv_frame;
+  int frame;            // the tile's frame when it lies in one, else -1
+  DepthCam cp, cq;      // that frame's cameras (valid when frame >= 0)
 };
 template <>
 struct SrcCtx<DT_DEPTH_F32> : DepthCtx {};
@@ -204,8 +206,8 @@ template <int DT>
 struct DepthPlanes {
   static constexpr bool BF = DT == DT_DEPTH_BF16;
   static constexpr int VEC = BF ? 8 : 4;
-  __device__ static inline void load(const SrcCtx<DT>& s, int64_t g0, int64_t n, float (&v)[7][VEC]) {
-    float d[3][VEC];
+  // d[0], d[1], d[2] = d_p, d_q, c of elements g0 .. g0 + VEC - 1 (0 past n)
+  __device__ static inline void load_raw(const SrcCtx<DT>& s, int64_t g0, int64_t n, float (&d)[3][VEC]) {
     if (g0 + VEC <= n) {
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
@@ -231,14 +233,34 @@ struct DepthPlanes {
             d[j][e] = (g0 + e < n) ? static_cast<const float*>(s.pl[j])[g0 + e] : 0.0f;
         }
     }
-    const DepthPair* P = s.dp;
-    const int W = P->width, H = P->rows, HW = P->frame_pixels, nf = P->n_frames;
+  }
+
+  // frame, row and column of element g0 (elements before the pair count as its first pixel)
+  __device__ static inline void position(const SrcCtx<DT>& s, int64_t g0, int& f, int& row, int& col) {
     int j = (int)(g0 - s.a);
     j = j < 0 ? 0 : j;
-    int f = div_floor(j, HW, P->inv_frame);
-    const int pin = j - f * HW;
-    int row = div_floor(pin, W, P->inv_width);
-    int col = pin - row * W;
+    f = div_floor(j, s.frame_pixels, s.inv_frame);
+    const int pin = j - f * s.frame_pixels;
+    row = div_floor(pin, s.width, s.inv_width);
+    col = pin - row * s.width;
+  }
+
+  // the next pixel (row-major, frame after frame)
+  __device__ static inline void advance(const SrcCtx<DT>& s, int& f, int& row, int& col) {
+    if (++col == s.width) {
+      col = 0;
+      if (++row == s.rows) {
+        row = 0;
+        ++f;
+      }
+    }
+  }
+
+  __device__ static inline void load(const SrcCtx<DT>& s, int64_t g0, int64_t n, float (&v)[7][VEC]) {
+    float d[3][VEC];
+    load_raw(s, g0, n, d);
+    int f, row, col;
+    position(s, g0, f, row, col);
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
       float x[3], y[3];
@@ -246,22 +268,14 @@ struct DepthPlanes {
         unproject(s.cp, (float)col, (float)row, d[0][e], x);
         unproject(s.cq, (float)col, (float)row, d[1][e], y);
       } else {
-        const int fc = f < nf ? f : nf - 1;
-        unproject(P->p[fc], (float)col, (float)row, d[0][e], x);
-        unproject(P->q[fc], (float)col, (float)row, d[1][e], y);
+        const int fc = f < s.n_frames ? f : s.n_frames - 1;
+        unproject(s.dp->p[fc], (float)col, (float)row, d[0][e], x);
+        unproject(s.dp->q[fc], (float)col, (float)row, d[1][e], y);
       }
       v[0][e] = x[0]; v[1][e] = x[1]; v[2][e] = x[2];
       v[3][e] = y[0]; v[4][e] = y[1]; v[5][e] = y[2];
       v[6][e] = d[2][e];
-      if (g0 + e >= s.a) {  // advance to the next pixel
-        if (++col == W) {
-          col = 0;
-          if (++row == H) {
-            row = 0;
-            ++f;
-          }
-        }
-      }
+      if (g0 + e >= s.a) advance(s, f, row, col);
     }
   }
 };
@@ -281,7 +295,13 @@ __device__ inline SrcCtx<DT> make_src(const void* const* pl, const Work& w, cons
     s.pl[2] = pl[2];
     s.dp = w.dpairs + td.pair;
     s.a = td.lo;
-    const int HW = uniform_i32(s.dp->frame_pixels), nf = uniform_i32(s.dp->n_frames);
+    s.width = uniform_i32(s.dp->width);
+    s.rows = uniform_i32(s.dp->rows);
+    s.frame_pixels = uniform_i32(s.dp->frame_pixels);
+    s.n_frames = uniform_i32(s.dp->n_frames);
+    s.inv_width = uniform_f32(s.dp->inv_width);
+    s.inv_frame = uniform_f32(s.dp->inv_frame);
+    const int HW = s.frame_pixels, nf = s.n_frames;
     const int64_t first = td.begin > td.lo ? td.begin : td.lo;
     const int f0 = (int)((first - td.lo) / HW), f1 = (int)((td.end - 1 - td.lo) / HW);
     s.frame = (f0 == f1 && f0 < nf && td.end > first) ? f0 : -1;
@@ -447,6 +467,90 @@ __device__ inline void block_store_f64(double (&acc)[N], double (*red)[NSTAT], d
 
 // ---------------------------------------------------------------- tile bodies
 
+// One point of the Gauss-Newton statistics: centred model point y, residual
+// r, weight w (0 for masked points); Huber weight branch-free.
+__device__ inline void gn_point(float (&a)[NSTAT], float y0, float y1, float y2, float r0, float r1, float r2, float w,
+                                float d2, float delta, float hd2) {
+  const float e2 = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
+  const float ie = __builtin_amdgcn_rsqf(e2);
+  const bool inl = e2 <= d2;
+  const float psi = inl ? 1.0f : delta * ie;
+  const float rho = inl ? 0.5f * e2 : fmaf(delta * e2, ie, -hd2);
+  const float om = w * psi;
+  const float oy0 = om * y0, oy1 = om * y1, oy2 = om * y2;
+  a[0] += om;
+  a[1] += oy0; a[2] += oy1; a[3] += oy2;
+  a[4] = fmaf(oy0, y0, a[4]); a[5] = fmaf(oy0, y1, a[5]); a[6] = fmaf(oy0, y2, a[6]);
+  a[7] = fmaf(oy1, y1, a[7]); a[8] = fmaf(oy1, y2, a[8]); a[9] = fmaf(oy2, y2, a[9]);
+  a[10] = fmaf(om, r0, a[10]); a[11] = fmaf(om, r1, a[11]); a[12] = fmaf(om, r2, a[12]);
+  a[13] = fmaf(oy1, r2, fmaf(-oy2, r1, a[13]));
+  a[14] = fmaf(oy2, r0, fmaf(-oy0, r2, a[14]));
+  a[15] = fmaf(oy0, r1, fmaf(-oy1, r0, a[15]));
+  a[16] = fmaf(oy0, r0, fmaf(oy1, r1, fmaf(oy2, r2, a[16])));
+  a[17] = fmaf(w, rho, a[17]);
+  a[18] += (inl && w > 0.0f) ? 1.0f : 0.0f;
+}
+
+// Gauss-Newton pass over a depth tile that lies in one frame: the pair's
+// current similarity is folded into each side's camera once per tile, so a
+// pixel costs one affine map per side on its ray:
+//   y_c = d_p (A ray_p) + b,  A = sR R_p, b = sR t_p + t - c;   q_c = d_q (R_q ray_q) + t_q - c.
+template <int DT, int WG, int ITEMS>
+__device__ inline void tile_gn_depth_frame(const Shape& sh, const SrcCtx<DT>& src, const TileDesc& td,
+                                           const PointParams& P, float (&a)[NSTAT]) {
+  using L = DepthPlanes<DT>;
+  constexpr int VEC = L::VEC;
+  const DepthCam& cp = src.cp;
+  const DepthCam& cq = src.cq;
+  float A[9], b[3], bq[3];
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+      A[3 * i + j] = fmaf(P.Mf[3 * i], cp.R[j], fmaf(P.Mf[3 * i + 1], cp.R[3 + j], P.Mf[3 * i + 2] * cp.R[6 + j]));
+    b[i] = fmaf(P.Mf[3 * i], cp.t[0], fmaf(P.Mf[3 * i + 1], cp.t[1], fmaf(P.Mf[3 * i + 2], cp.t[2], P.tcf[i])));
+    bq[i] = cq.t[i] - P.cf[i];
+  }
+  const float tau = sh.tau, delta = sh.delta_f;
+  const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
+  const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+  const bool check_finite = P.nonfinite != 0;
+#pragma unroll 1
+  for (int it = 0; it < ITEMS; ++it) {
+    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+    if (rel0 >= end_rel) break;
+    float d[3][VEC];
+    L::load_raw(src, td.begin + rel0, sh.n_points, d);
+    int f, row, col;
+    L::position(src, td.begin + rel0, f, row, col);
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
+      const float fc = (float)col, fr = (float)row;
+      const float rxp = fmaf(fc, cp.ifx, cp.ox), ryp = fmaf(fr, cp.ify, cp.oy);
+      const float rxq = fmaf(fc, cq.ifx, cq.ox), ryq = fmaf(fr, cq.ify, cq.oy);
+      float y[3], q[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        y[i] = fmaf(d[0][e], fmaf(A[3 * i], rxp, fmaf(A[3 * i + 1], ryp, A[3 * i + 2])), b[i]);
+        q[i] = fmaf(d[1][e], fmaf(cq.R[3 * i], rxq, fmaf(cq.R[3 * i + 1], ryq, cq.R[3 * i + 2])), bq[i]);
+      }
+      bool ok = in;
+      if (check_finite) ok = ok && __builtin_isfinite(y[0] + y[1] + y[2] + q[0] + q[1] + q[2]) && __builtin_isfinite(d[2][e]);
+      const float c = d[2][e];
+      const float w = (ok && c >= tau) ? c : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        y[i] = ok ? y[i] : 0.0f;
+        q[i] = ok ? q[i] : 0.0f;
+      }
+      gn_point(a, y[0], y[1], y[2], y[0] - q[0], y[1] - q[1], y[2] - q[2], w, d2, delta, hd2);
+      if (rel0 + e >= lo_rel) L::advance(src, f, row, col);
+    }
+  }
+}
+
+
 // Gauss-Newton pass over one tile. Every quantity is formed in FP32 in
 // coordinates centred on the pair's centre c (the weighted target centroid):
 //   y_c = Mf p + (t - c),  q_c = q - c,  r = y_c - q_c,
@@ -463,6 +567,13 @@ __device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const Tile
   float a[NSTAT];
 #pragma unroll
   for (int j = 0; j < NSTAT; ++j) a[j] = 0.0f;
+  if constexpr (DT == DT_DEPTH_F32 || DT == DT_DEPTH_BF16) {
+    if (P.active && pl.frame >= 0) {
+      tile_gn_depth_frame<DT, WG, ITEMS>(sh, pl, td, P, a);
+      block_store_f32<WG>(a, red, out);
+      return;
+    }
+  }
   if (P.active) {
     const float tau = sh.tau, delta = sh.delta_f;
     const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
@@ -500,27 +611,8 @@ __device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const Tile
         const float y0 = fmaf(P.Mf[0], px, fmaf(P.Mf[1], py, fmaf(P.Mf[2], pz, P.tcf[0])));
         const float y1 = fmaf(P.Mf[3], px, fmaf(P.Mf[4], py, fmaf(P.Mf[5], pz, P.tcf[1])));
         const float y2 = fmaf(P.Mf[6], px, fmaf(P.Mf[7], py, fmaf(P.Mf[8], pz, P.tcf[2])));
-        const float r0 = y0 - (v[3][e] - P.cf[0]);
-        const float r1 = y1 - (v[4][e] - P.cf[1]);
-        const float r2 = y2 - (v[5][e] - P.cf[2]);
-        const float e2 = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
-        const float ie = __builtin_amdgcn_rsqf(e2);
-        const bool inl = e2 <= d2;
-        const float psi = inl ? 1.0f : delta * ie;
-        const float rho = inl ? 0.5f * e2 : fmaf(delta * e2, ie, -hd2);
-        const float om = w * psi;
-        const float oy0 = om * y0, oy1 = om * y1, oy2 = om * y2;
-        a[0] += om;
-        a[1] += oy0; a[2] += oy1; a[3] += oy2;
-        a[4] = fmaf(oy0, y0, a[4]); a[5] = fmaf(oy0, y1, a[5]); a[6] = fmaf(oy0, y2, a[6]);
-        a[7] = fmaf(oy1, y1, a[7]); a[8] = fmaf(oy1, y2, a[8]); a[9] = fmaf(oy2, y2, a[9]);
-        a[10] = fmaf(om, r0, a[10]); a[11] = fmaf(om, r1, a[11]); a[12] = fmaf(om, r2, a[12]);
-        a[13] = fmaf(oy1, r2, fmaf(-oy2, r1, a[13]));
-        a[14] = fmaf(oy2, r0, fmaf(-oy0, r2, a[14]));
-        a[15] = fmaf(oy0, r1, fmaf(-oy1, r0, a[15]));
-        a[16] = fmaf(oy0, r0, fmaf(oy1, r1, fmaf(oy2, r2, a[16])));
-        a[17] = fmaf(w, rho, a[17]);
-        a[18] += (inl && w > 0.0f) ? 1.0f : 0.0f;
+        gn_point(a, y0, y1, y2, y0 - (v[3][e] - P.cf[0]), y1 - (v[4][e] - P.cf[1]), y2 - (v[5][e] - P.cf[2]), w,
+                 d2, delta, hd2);
       }
     }
   }
