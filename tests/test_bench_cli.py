@@ -20,10 +20,11 @@ def test_measured_traffic_only_for_its_sources_and_shape():
     sys.path.insert(0, ROOT)
     import bench
     m = bench.MEASURED_TRAFFIC
-    # within a few percent of the algorithmic bytes of one pass (28 B per stored point)
-    assert 1.0 <= m["bytes_per_launch"] / (28 * 32082542) < 1.05
+    for shape, b in m["bytes_per_launch"].items():
+        # within a few percent of the algorithmic bytes of one pass (28 B per stored point)
+        assert 1.0 <= b / (28 * 32082542) < 1.05
+        if bench.kpass_sources_sha256() == m["sources_sha256"]:
+            assert bench.measured_traffic(shape) == b
+        else:
+            assert bench.measured_traffic(shape) is None
     assert bench.measured_traffic((1, 1, 1)) is None
-    if bench.kpass_sources_sha256() == m["sources_sha256"]:
-        assert bench.measured_traffic(m["tuning"]) == m["bytes_per_launch"]
-    else:
-        assert bench.measured_traffic(m["tuning"]) is None
