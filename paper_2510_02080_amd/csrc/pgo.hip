@@ -52,11 +52,19 @@ struct PgoDev {
   // updates: target t (0..m-1 diagonal of position t, m + b off-diagonal block b) gets
   // -= L_a L_b^T for (a, b) in up_a/up_b[up_ptr[t]..]; a, b index blocks (always off-diagonal)
   const int32_t* up_ptr; const int32_t* up_a; const int32_t* up_b;
-  // level schedule (from the leaves): columns, and per level the flattened
-  // update targets (diagonal c or m + off-diagonal block) and off-diagonal blocks
+  // solve schedule: every column, by level from the leaves
   const int32_t* lev_ptr; const int32_t* lev_col;
+  // factor schedule of the sparse part (columns below p0): per level its columns, the
+  // flattened update targets (diagonal c or m + off-diagonal block) and off-diagonal blocks
+  int32_t nflev;
+  const int32_t* flev_ptr; const int32_t* flev_col;
   const int32_t* lt_ptr; const int32_t* lt_tgt;
   const int32_t* lb_ptr; const int32_t* lb_blk;
+  // dense trailing clique: columns p0 .. m-1 (K of them) hold every block below the
+  // diagonal (block of rows p0+i, column p0+k at clique_block(i, k)); the clique's
+  // targets get the updates of sparse columns (dt lists) before the dense factorisation
+  int32_t K, p0, cp0, n_dt;  // cp0: first block of column p0
+  const int32_t* dt_tgt; const int32_t* dt_ptr; const int32_t* dup_a; const int32_t* dup_b;
   // rows of L for the forward solve: blocks (c, k), k < c
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
@@ -174,21 +182,99 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // One Gauss-Newton iteration on one workgroup: chi^2, assembly, factorisation,
 // solves, update. `it` indexes the chi^2 record.
-__global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, double lambda, int it, int update,
-                                                       int lm) {
-  __shared__ double sh[PGO_WG / 64 + 1];
-  __shared__ int s_fail;
-  const int tid = threadIdx.x;
+// Largest dense clique factored by the right-looking step (its column panel lives in LDS).
+constexpr int PGO_KMAX = 96;
+
+// S -= sum_q L_a L_b^T over one target's update list [q0, q1) (blocks a = ua[q], b = ub[q]),
+// by one wavefront, lane = element (r, s) of the 7x7 block, in list order. The block
+// indices are fetched 64 at a time, one per lane, and read back from lanes (uniform),
+// so the only dependent loads left are the blocks; four updates are in flight.
+__device__ inline void update_target(const PgoDev& d, int target, int q0, int q1, const int32_t* ua,
+                                     const int32_t* ub, int lane) {
+  const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
+  double* dst = target < d.m ? d.Ld + 49 * target + (lane < 49 ? lane : 0) : d.Lb + 49 * (target - d.m) + (lane < 49 ? lane : 0);
+  const double old = *dst;  // issued first: its latency overlaps the update loads
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  for (int qb = q0; qb < q1; qb += 64) {
+    const int nq = min(64, q1 - qb);
+    const int ia = lane < nq ? ua[qb + lane] : 0;
+    const int ib = lane < nq ? ub[qb + lane] : 0;
+    int u = 0;
+    for (; u + 4 <= nq; u += 4) {
+      const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
+      const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
+      const double* A1 = d.Lb + 49 * __shfl(ia, u + 1, 64) + 7 * r;
+      const double* B1 = d.Lb + 49 * __shfl(ib, u + 1, 64) + 7 * s;
+      const double* A2 = d.Lb + 49 * __shfl(ia, u + 2, 64) + 7 * r;
+      const double* B2 = d.Lb + 49 * __shfl(ib, u + 2, 64) + 7 * s;
+      const double* A3 = d.Lb + 49 * __shfl(ia, u + 3, 64) + 7 * r;
+      const double* B3 = d.Lb + 49 * __shfl(ib, u + 3, 64) + 7 * s;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        acc0 += A0[k] * B0[k];
+        acc1 += A1[k] * B1[k];
+        acc2 += A2[k] * B2[k];
+        acc3 += A3[k] * B3[k];
+      }
+    }
+    for (; u < nq; ++u) {
+      const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
+      const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
+#pragma unroll
+      for (int k = 0; k < 7; ++k) acc0 += A0[k] * B0[k];
+    }
+  }
+  if (lane < 49) *dst = old - ((acc0 + acc1) + (acc2 + acc3));
+}
+
+// In-place Cholesky of one 7x7 diagonal block by one wavefront: lane 7r + s holds
+// element (r, s); column j is scaled and broadcast by cross-lane reads, then the
+// trailing elements are updated. The upper triangle is zeroed. False if a pivot
+// is not positive.
+__device__ inline bool chol7_wave(double* D, int lane) {
+  const int r = lane / 7, s = lane % 7;
+  double a = lane < 49 ? D[lane] : 0.0;
+  bool ok = true;
+  for (int j = 0; j < 7; ++j) {
+    const double djj = __shfl(a, 8 * j, 64);
+    if (!(djj > 0.0)) { ok = false; break; }
+    const double ljj = sqrt(djj);
+    if (lane < 49 && s == j) a = r == j ? ljj : (r > j ? a / ljj : a);
+    const double lrj = __shfl(a, lane < 49 ? 7 * r + j : 0, 64);
+    const double lsj = __shfl(a, lane < 49 ? 7 * s + j : 0, 64);
+    if (lane < 49 && s > j && r >= s) a -= lrj * lsj;
+  }
+  if (lane < 49) D[lane] = s > r ? 0.0 : a;
+  return ok;
+}
+
+// One row of L_ij = S_ij L_jj^{-T} (forward substitution against the diagonal
+// factor D), in place; optionally copied to `copy` as well.
+__device__ inline void trsm_row(double* row, const double* D, double* copy) {
+  double y[7];
+  for (int j = 0; j < 7; ++j) {
+    double v = row[j];
+    for (int k = 0; k < j; ++k) v -= y[k] * D[7 * j + k];
+    y[j] = v / D[8 * j];
+  }
+  for (int j = 0; j < 7; ++j) row[j] = y[j];
+  if (copy)
+    for (int j = 0; j < 7; ++j) copy[j] = y[j];
+}
+
+// Clique block (i, k), i > k (clique-local indices): column p0 + k holds every row
+// below it, in order, right after the blocks of the clique's earlier columns.
+__device__ inline int clique_block(const PgoDev& d, int i, int k) {
+  return d.cp0 + k * (d.K - 1) - k * (k - 1) / 2 + (i - k - 1);
+}
+
+// Assembly of the normal equations from the per-edge linearisations:
+// independent sums, spread over the whole chip.
+__global__ __launch_bounds__(256) void k_pgo_assemble(PgoDev d, double lambda, int lm) {
   if (*d.status != 0) return;
-  // chi^2 at the linearisation point (fixed order)
-  double part = 0.0;
-  for (int k = tid; k < d.n_edges; k += PGO_WG) part += d.r2[k];
-  const double c2 = wg_sum(part, sh);
-  if (tid == 0) d.chi2[it] = c2;
-  if (!update) return;
-  if (tid == 0) s_fail = 0;
+  const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
   // ---- assembly (diagonal blocks, off-diagonal blocks, gradient)
-  for (int x = tid; x < d.m * 49; x += PGO_WG) {
+  for (int x = gt; x < d.m * 49; x += gs) {
     const int c = x / 49, a = x % 49;
     double s = 0.0;
     for (int q = d.dg_ptr[c]; q < d.dg_ptr[c + 1]; ++q) s += d.M[49 * d.dg_edge[q] + a];
@@ -196,95 +282,51 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     if (lambda > 0.0 && a % 8 == 0) s += lambda * s;
     d.Ld[x] = s;
   }
-  for (int x = tid; x < d.nblk * 49; x += PGO_WG) {
+  for (int x = gt; x < d.nblk * 49; x += gs) {
     const int b = x / 49, a = x % 49;
     double s = 0.0;
     for (int q = d.ob_ptr[b]; q < d.ob_ptr[b + 1]; ++q) s -= d.M[49 * d.ob_edge[q] + a];
     d.Lb[x] = s;
   }
-  for (int x = tid; x < d.m * 7; x += PGO_WG) {
+  for (int x = gt; x < d.m * 7; x += gs) {
     const int c = x / 7, a = x % 7;
     double s = 0.0;
     for (int q = d.gv_ptr[c]; q < d.gv_ptr[c + 1]; ++q) s += (double)d.gv_sign[q] * d.v[7 * d.gv_edge[q] + a];
     d.g[x] = -s;  // right-hand side -g
     if (lm) d.gsave[x] = -s;
   }
+}
+
+// chi^2 at the linearisation point, then (update) the sparse columns' factorisation
+// level by level, by one workgroup.
+__global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int update) {
+  __shared__ double sh[PGO_WG / 64 + 1];
+  __shared__ int s_fail;
+  const int tid = threadIdx.x;
+  if (*d.status != 0) return;
+  double part = 0.0;
+  for (int k = tid; k < d.n_edges; k += PGO_WG) part += d.r2[k];
+  const double c2 = wg_sum(part, sh);  // fixed order
+  if (tid == 0) d.chi2[it] = c2;
+  if (!update) return;
+  if (tid == 0) s_fail = 0;
   __syncthreads();
-  // ---- factorisation, level by level
-  for (int l = 0; l < d.nlev; ++l) {
-    const int c0 = d.lev_ptr[l], c1 = d.lev_ptr[l + 1];
-    // (A) every update target of this level (diagonal and off-diagonal blocks of
-    // its columns): one wavefront per target, lane = element (r, s) of the 7x7
-    // block: S -= sum_k L_a L_b^T over the target's update list, in list order.
-    // The list's block indices are fetched 64 at a time, one per lane, and read
-    // back from lanes (uniform), so the only dependent loads left are the
-    // blocks themselves; four updates are in flight.
+  // ---- factorisation: the sparse part level by level, then the dense clique
+  const int lane = tid & 63, wv = tid >> 6;
+  for (int l = 0; l < d.nflev; ++l) {
+    const int c0 = d.flev_ptr[l], c1 = d.flev_ptr[l + 1];
+    // (A) every update target of this level (diagonal and off-diagonal blocks of its columns)
     {
       const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
-      const int lane = tid & 63, wv = tid >> 6;
-      const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
       for (int ti = wv; ti < nt; ti += PGO_WG / 64) {
         const int target = d.lt_tgt[t0 + ti];
-        const int q0 = d.up_ptr[target], q1 = d.up_ptr[target + 1];
-        double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
-        for (int qb = q0; qb < q1; qb += 64) {
-          const int nq = min(64, q1 - qb);
-          const int ia = lane < nq ? d.up_a[qb + lane] : 0;
-          const int ib = lane < nq ? d.up_b[qb + lane] : 0;
-          int u = 0;
-          for (; u + 4 <= nq; u += 4) {
-            const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
-            const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
-            const double* A1 = d.Lb + 49 * __shfl(ia, u + 1, 64) + 7 * r;
-            const double* B1 = d.Lb + 49 * __shfl(ib, u + 1, 64) + 7 * s;
-            const double* A2 = d.Lb + 49 * __shfl(ia, u + 2, 64) + 7 * r;
-            const double* B2 = d.Lb + 49 * __shfl(ib, u + 2, 64) + 7 * s;
-            const double* A3 = d.Lb + 49 * __shfl(ia, u + 3, 64) + 7 * r;
-            const double* B3 = d.Lb + 49 * __shfl(ib, u + 3, 64) + 7 * s;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) {
-              acc0 += A0[k] * B0[k];
-              acc1 += A1[k] * B1[k];
-              acc2 += A2[k] * B2[k];
-              acc3 += A3[k] * B3[k];
-            }
-          }
-          for (; u < nq; ++u) {
-            const double* A0 = d.Lb + 49 * __shfl(ia, u, 64) + 7 * r;
-            const double* B0 = d.Lb + 49 * __shfl(ib, u, 64) + 7 * s;
-#pragma unroll
-            for (int k = 0; k < 7; ++k) acc0 += A0[k] * B0[k];
-          }
-        }
-        if (lane < 49) {
-          double* dst = target < d.m ? d.Ld + 49 * target + lane : d.Lb + 49 * (target - d.m) + lane;
-          *dst -= (acc0 + acc1) + (acc2 + acc3);
-        }
+        update_target(d, target, d.up_ptr[target], d.up_ptr[target + 1], d.up_a, d.up_b, lane);
       }
     }
     __syncthreads();
-    // (B) Cholesky of each diagonal block of the level: one wavefront per block,
-    // lane 7r + s holds element (r, s) in a register; column j is scaled and
-    // broadcast by cross-lane reads, then the trailing elements are updated.
-    {
-      const int lane = tid & 63, wv = tid >> 6;
-      const int r = lane / 7, s = lane % 7;
-      for (int cc = c0 + wv; cc < c1; cc += PGO_WG / 64) {
-        double* D = d.Ld + 49 * d.lev_col[cc];
-        double a = lane < 49 ? D[lane] : 0.0;
-        bool ok = true;
-        for (int j = 0; j < 7; ++j) {
-          const double djj = __shfl(a, 8 * j, 64);
-          if (!(djj > 0.0)) { ok = false; break; }
-          const double ljj = sqrt(djj);
-          if (lane < 49 && s == j) a = r == j ? ljj : (r > j ? a / ljj : a);
-          const double lrj = __shfl(a, lane < 49 ? 7 * r + j : 0, 64);
-          const double lsj = __shfl(a, lane < 49 ? 7 * s + j : 0, 64);
-          if (lane < 49 && s > j && r >= s) a -= lrj * lsj;
-        }
-        if (lane < 49) D[lane] = s > r ? 0.0 : a;
-        if (!ok && lane == 0) s_fail = 1;
-      }
+    // (B) Cholesky of each diagonal block of the level: one wavefront per block
+    for (int cc = c0 + wv; cc < c1; cc += PGO_WG / 64) {
+      if (!chol7_wave(d.Ld + 49 * d.flev_col[cc], lane) && lane == 0) s_fail = 1;
     }
     __syncthreads();
     if (s_fail) break;
@@ -292,26 +334,91 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_iterate(PgoDev d, s3a_sim3* T, d
     {
       const int b0 = d.lb_ptr[l], nb = d.lb_ptr[l + 1] - b0;
       for (int x = tid; x < nb * 7; x += PGO_WG) {
-        const int b = d.lb_blk[b0 + x / 7];
-        const double* D = d.Ld + 49 * d.blk_col[b];
-        double* row = d.Lb + 49 * b + 7 * (x % 7);
-        double y[7];
-        for (int j = 0; j < 7; ++j) {
-          double v = row[j];
-          for (int k = 0; k < j; ++k) v -= y[k] * D[7 * j + k];
-          y[j] = v / D[8 * j];
-        }
-        for (int j = 0; j < 7; ++j) row[j] = y[j];
+        const int bb = d.lb_blk[b0 + x / 7];
+        trsm_row(d.Lb + 49 * bb + 7 * (x % 7), d.Ld + 49 * d.blk_col[bb], nullptr);
       }
     }
     __syncthreads();
+  }
+  if (s_fail && tid == 0) *d.status = 2;
+}
+
+// The sparse columns' updates of every block of the clique: independent targets,
+// one wavefront each, spread over the whole chip.
+__global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
+  if (*d.status != 0) return;
+  const int ti = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
+  if (ti >= d.n_dt) return;
+  update_target(d, d.dt_tgt[ti], d.dt_ptr[ti], d.dt_ptr[ti + 1], d.dup_a, d.dup_b, lane);
+}
+
+// The clique's right-looking factorisation, the two triangular solves and the
+// update T <- Exp(dx) T, by one workgroup.
+__global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, double lambda, int lm) {
+  __shared__ double sh[PGO_WG / 64 + 1];
+  __shared__ int s_fail;
+  __shared__ double panel[49 * (PGO_KMAX - 1)];  // the clique column being applied
+  const int tid = threadIdx.x;
+  if (*d.status != 0) return;
+  if (tid == 0) s_fail = 0;
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6;
+  if (d.K > 0) {
+    // (D2) right-looking over the clique, one node column j at a time: factor the
+    // diagonal block, solve the column's blocks (kept in LDS as well), then update
+    // every trailing block (i, i'), j < i' <= i, by L_ij L_i'j^T: one wavefront per
+    // block, lane = element.
+    const int K = d.K;
+    for (int j = 0; j < K; ++j) {
+      const int c = d.p0 + j;
+      if (wv == 0 && !chol7_wave(d.Ld + 49 * c, lane) && lane == 0) s_fail = 1;
+      __syncthreads();
+      if (s_fail) break;
+      const int nrow = K - 1 - j;
+      for (int x = tid; x < nrow * 7; x += PGO_WG) {
+        const int i = j + 1 + x / 7;
+        trsm_row(d.Lb + 49 * clique_block(d, i, j) + 7 * (x % 7), d.Ld + 49 * c, panel + 49 * (i - j - 1) + 7 * (x % 7));
+      }
+      __syncthreads();
+      const int nt = nrow * (nrow + 1) / 2;
+      const int r = lane < 49 ? lane / 7 : 0, sc = lane < 49 ? lane % 7 : 0;
+      // eight targets per wavefront at a time: their loads are issued before any store
+      constexpr int NB = 8;
+      for (int tb = wv * NB; tb < nt; tb += (PGO_WG / 64) * NB) {
+        double* dst[NB];
+        double old[NB];
+        int ia[NB], ib[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const int ti = tb + q < nt ? tb + q : nt - 1;
+          // ti -> (a, b), 0 <= b <= a < nrow, row-major over the lower triangle
+          int a = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
+          a -= (a * (a + 1) / 2 > ti) ? 1 : 0;
+          a += ((a + 1) * (a + 2) / 2 <= ti) ? 1 : 0;
+          ia[q] = a;
+          ib[q] = ti - a * (a + 1) / 2;
+          const int i = j + 1 + ia[q], i2 = j + 1 + ib[q];
+          dst[q] = (i == i2) ? d.Ld + 49 * (d.p0 + i) : d.Lb + 49 * clique_block(d, i, i2);
+          old[q] = lane < 49 ? dst[q][lane] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+          const double* Pa = panel + 49 * ia[q] + 7 * r;
+          const double* Pb = panel + 49 * ib[q] + 7 * sc;
+          double acc = 0.0;
+#pragma unroll
+          for (int u = 0; u < 7; ++u) acc += Pa[u] * Pb[u];
+          if (lane < 49 && tb + q < nt) dst[q][lane] = old[q] - acc;
+        }
+      }
+      __syncthreads();
+    }
   }
   if (s_fail) {
     if (tid == 0) *d.status = 2;
     return;
   }
   // ---- forward solve L y = -g, levels from the leaves; one wavefront per column
-  const int lane = tid & 63, wv = tid >> 6;
   for (int l = 0; l < d.nlev; ++l) {
     for (int cc = d.lev_ptr[l] + wv; cc < d.lev_ptr[l + 1]; cc += PGO_WG / 64) {
       const int c = d.lev_col[cc];
@@ -398,9 +505,10 @@ struct PgoWorkspace {
 namespace {
 
 struct Symbolic {
-  int m = 0, nblk = 0, nlev = 0;
+  int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, cp0 = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
-      up_ptr, up_a, up_b, lev_ptr, lev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk, chain;
+      up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk,
+      chain, dt_tgt, dt_ptr, dup_a, dup_b;
   std::vector<int8_t> gv_sign;
 };
 
@@ -530,19 +638,64 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   S.lev_col.resize(m);
   std::vector<int> fill(S.lev_ptr.begin(), S.lev_ptr.end() - 1);
   for (int c = 0; c < m; ++c) S.lev_col[fill[lev[c]]++] = c;
-  S.lt_ptr.assign(nlev + 1, 0);
-  S.lb_ptr.assign(nlev + 1, 0);
+  // dense trailing clique: the last K columns each hold every row below them
+  int K = 0;
+  for (int c = m - 1; c >= 0 && (int)cs[c].size() == m - 1 - c; --c) ++K;
+  if (K < 8) K = 0;
+  if (K > PGO_KMAX) K = PGO_KMAX;
+  // every clique pair's block sits where the device computes it (column c holds its rows
+  // in order, and the clique's columns are consecutive); otherwise the clique is left
+  // to the sparse schedule
+  if (K > 0) {
+    const int q0 = m - K, cp0 = S.col_ptr[q0];
+    for (int k = 0; k < K && K > 0; ++k)
+      for (int i = k + 1; i < K; ++i)
+        if (block_of(q0 + i, q0 + k) != cp0 + k * (K - 1) - k * (k - 1) / 2 + (i - k - 1)) {
+          K = 0;
+          break;
+        }
+  }
+  const int p0 = m - K;
+  S.K = K;
+  S.p0 = p0;
+  S.cp0 = K > 0 ? S.col_ptr[p0] : 0;
+  // factor schedule of the sparse columns (levels without one are dropped)
+  S.flev_ptr.assign(1, 0);
+  S.lt_ptr.assign(1, 0);
+  S.lb_ptr.assign(1, 0);
   for (int l = 0; l < nlev; ++l) {
+    bool any = false;
     for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
       const int c = S.lev_col[q];
+      if (c >= p0) continue;
+      any = true;
+      S.flev_col.push_back(c);
       S.lt_tgt.push_back(c);
       for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) {
         S.lt_tgt.push_back(m + b);
         S.lb_blk.push_back(b);
       }
     }
-    S.lt_ptr[l + 1] = (int32_t)S.lt_tgt.size();
-    S.lb_ptr[l + 1] = (int32_t)S.lb_blk.size();
+    if (!any) continue;
+    S.flev_ptr.push_back((int32_t)S.flev_col.size());
+    S.lt_ptr.push_back((int32_t)S.lt_tgt.size());
+    S.lb_ptr.push_back((int32_t)S.lb_blk.size());
+  }
+  S.nflev = (int)S.flev_ptr.size() - 1;
+  // the clique: block map, and each of its targets' updates from sparse columns
+  S.dt_ptr.assign(1, 0);
+  for (int c = p0; c < m; ++c) {
+    std::vector<int> tg{c};
+    for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) tg.push_back(m + b);
+    for (int t : tg) {
+      S.dt_tgt.push_back(t);
+      for (int q = S.up_ptr[t]; q < S.up_ptr[t + 1]; ++q)
+        if (S.blk_col[S.up_a[q]] < p0) {
+          S.dup_a.push_back(S.up_a[q]);
+          S.dup_b.push_back(S.up_b[q]);
+        }
+      S.dt_ptr.push_back((int32_t)S.dup_a.size());
+    }
   }
   // rows of L (blocks (c, k), k < c) for the forward solve
   std::vector<std::vector<int>> rows(m);
@@ -597,6 +750,25 @@ int fail(int* last_hip, hipError_t e) {
 
 namespace {
 
+// One damped solve and update of the poses (or, without update, only chi^2 at the
+// current linearisation): assembly across the chip, the sparse factorisation in one
+// workgroup, the clique's sparse-column updates across the chip, then the clique, the
+// solves and the update in one workgroup.
+hipError_t launch_iteration(const PgoDev& d, s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
+  if (!update || d.m == 0) {
+    hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(PGO_WG), 0, st, d, it, 0);
+    return hipGetLastError();
+  }
+  const int64_t work = std::max<int64_t>((int64_t)d.nblk * 49, (int64_t)d.m * 49);
+  const int ga = (int)std::min<int64_t>((work + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pgo_assemble, dim3(ga), dim3(256), 0, st, d, lambda, lm);
+  hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(PGO_WG), 0, st, d, it, 1);
+  if (d.K > 0 && d.n_dt > 0)
+    hipLaunchKernelGGL(k_pgo_clique_updates, dim3((d.n_dt + 3) / 4), dim3(256), 0, st, d);
+  hipLaunchKernelGGL(k_pgo_finish, dim3(1), dim3(PGO_WG), 0, st, d, T, lambda, lm);
+  return hipGetLastError();
+}
+
 double huber_energy(const std::vector<double>& r2, double delta) {
   double F = 0.0;
   for (double x : r2) {
@@ -607,7 +779,7 @@ double huber_energy(const std::vector<double>& r2, double delta) {
 }
 
 // Levenberg-Marquardt driver: every trial is one damped solve on the device
-// (k_pgo_iterate, which also leaves the predicted reduction), a
+// (launch_iteration, which also leaves the predicted reduction), a
 // linearisation at the trial poses into the second buffer set, and a read of
 // the trial's per-edge e^T Omega e to decide on the host.
 int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edges, const s3a_sim3* T_meas,
@@ -644,8 +816,7 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
       e = hipMemcpyAsync(ws->T_bak, T, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<uint32_t*>(cur.status), 1, st);
       if (e != hipSuccess) return fail(last_hip, e);
-      hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, cur, T, lam, it, 1, 1);
-      if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+      if ((e = launch_iteration(cur, T, lam, it, 1, 1, st)) != hipSuccess) return fail(last_hip, e);
       int32_t fst = 0;
       double pred = 0.0;
       e = hipMemcpyAsync(&fst, cur.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -759,7 +930,10 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.gv_ptr.size()) + bytes_of<int32_t>(S.gv_edge.size()) + bytes_of<int8_t>(S.gv_sign.size());
     total += bytes_of<int32_t>(S.up_ptr.size()) + bytes_of<int32_t>(S.up_a.size()) * 2;
     total += bytes_of<int32_t>(S.lev_ptr.size()) + bytes_of<int32_t>(S.lev_col.size());
-    total += bytes_of<int32_t>(S.lt_ptr.size()) + bytes_of<int32_t>(S.lt_tgt.size());
+    total += bytes_of<int32_t>(S.flev_ptr.size()) + bytes_of<int32_t>(S.flev_col.size() + 1);
+    total += bytes_of<int32_t>(S.dt_tgt.size() + 1) + bytes_of<int32_t>(S.dt_ptr.size());
+    total += bytes_of<int32_t>(S.dup_a.size() + 1) * 2;
+    total += bytes_of<int32_t>(S.lt_ptr.size()) + bytes_of<int32_t>(S.lt_tgt.size() + 1);
     total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.chain.size() + 4);
@@ -781,6 +955,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     char* c = static_cast<char*>(buf);
     PgoDev& d = ws->dev;
     d.n_nodes = n_nodes; d.n_edges = E; d.m = m; d.gauge = p.gauge; d.nblk = nb; d.nlev = S.nlev;
+    d.nflev = S.nflev; d.K = S.K; d.p0 = S.p0; d.cp0 = S.cp0; d.n_dt = (int32_t)S.dt_tgt.size();
     std::vector<int32_t> ei(E), ej(E);
     for (int k = 0; k < E; ++k) { ei[k] = ij[2 * k]; ej[k] = ij[2 * k + 1]; }
     std::vector<std::pair<void*, std::pair<const void*, size_t>>> up;
@@ -806,8 +981,14 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_upb = carve<int32_t>(c, S.up_b.size()); put(p_upb, S.up_b); d.up_b = p_upb;
     int32_t* p_lvp = carve<int32_t>(c, S.lev_ptr.size()); put(p_lvp, S.lev_ptr); d.lev_ptr = p_lvp;
     int32_t* p_lvc = carve<int32_t>(c, S.lev_col.size()); put(p_lvc, S.lev_col); d.lev_col = p_lvc;
+    int32_t* p_flp = carve<int32_t>(c, S.flev_ptr.size()); put(p_flp, S.flev_ptr); d.flev_ptr = p_flp;
+    int32_t* p_flc = carve<int32_t>(c, S.flev_col.size() + 1); put(p_flc, S.flev_col); d.flev_col = p_flc;
+    int32_t* p_dtt = carve<int32_t>(c, S.dt_tgt.size() + 1); put(p_dtt, S.dt_tgt); d.dt_tgt = p_dtt;
+    int32_t* p_dtp = carve<int32_t>(c, S.dt_ptr.size()); put(p_dtp, S.dt_ptr); d.dt_ptr = p_dtp;
+    int32_t* p_dua = carve<int32_t>(c, S.dup_a.size() + 1); put(p_dua, S.dup_a); d.dup_a = p_dua;
+    int32_t* p_dub = carve<int32_t>(c, S.dup_b.size() + 1); put(p_dub, S.dup_b); d.dup_b = p_dub;
     int32_t* p_ltp = carve<int32_t>(c, S.lt_ptr.size()); put(p_ltp, S.lt_ptr); d.lt_ptr = p_ltp;
-    int32_t* p_ltt = carve<int32_t>(c, S.lt_tgt.size()); put(p_ltt, S.lt_tgt); d.lt_tgt = p_ltt;
+    int32_t* p_ltt = carve<int32_t>(c, S.lt_tgt.size() + 1); put(p_ltt, S.lt_tgt); d.lt_tgt = p_ltt;
     int32_t* p_lbp = carve<int32_t>(c, S.lb_ptr.size()); put(p_lbp, S.lb_ptr); d.lb_ptr = p_lbp;
     int32_t* p_lbb = carve<int32_t>(c, S.lb_blk.size() + 1); put(p_lbb, S.lb_blk); d.lb_blk = p_lbb;
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
@@ -858,8 +1039,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
       if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
     }
     if (update && d.m == 0) continue;
-    hipLaunchKernelGGL(k_pgo_iterate, dim3(1), dim3(PGO_WG), 0, st, d, T, p.lambda, it, update, 0);
-    if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+    if ((e = launch_iteration(d, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
   }
   if (report) {
     std::vector<double> chi(p.iters + 1, 0.0);
