@@ -71,6 +71,7 @@ struct PgoDev {
   const int32_t* chain; int32_t n_chain;
   // numeric storage
   double* Ld;     // [m][49] diagonal blocks (lower Cholesky factor after factorisation)
+  double* Di;     // [m][49] inverses of the factored diagonal blocks (lower triangular)
   double* Lb;     // [nblk][49]
   double* g;      // [m][7]  gradient, then solution
   double* M;      // [E][49] per-edge psi A^T Omega A
@@ -227,38 +228,74 @@ __device__ inline void update_target(const PgoDev& d, int target, int q0, int q1
   if (lane < 49) *dst = old - ((acc0 + acc1) + (acc2 + acc3));
 }
 
-// In-place Cholesky of one 7x7 diagonal block by one wavefront: lane 7r + s holds
-// element (r, s); column j is scaled and broadcast by cross-lane reads, then the
-// trailing elements are updated. The upper triangle is zeroed. False if a pivot
-// is not positive.
-__device__ inline bool chol7_wave(double* D, int lane) {
-  const int r = lane / 7, s = lane % 7;
-  double a = lane < 49 ? D[lane] : 0.0;
+// In-place Cholesky of one 7x7 diagonal block by one lane (row by row), zeroing
+// the upper triangle, and the inverse of the factor into Di (and `copy` when
+// given): each diagonal element is inverted once, so the triangular solves that
+// use the block need no divisions. False if a pivot is not positive.
+__device__ inline bool chol7_lane(double* D, double* Di, double* copy) {
+  double L[7][7];
+  double rinv[7];
   bool ok = true;
-  for (int j = 0; j < 7; ++j) {
-    const double djj = __shfl(a, 8 * j, 64);
-    if (!(djj > 0.0)) { ok = false; break; }
-    const double ljj = sqrt(djj);
-    if (lane < 49 && s == j) a = r == j ? ljj : (r > j ? a / ljj : a);
-    const double lrj = __shfl(a, lane < 49 ? 7 * r + j : 0, 64);
-    const double lsj = __shfl(a, lane < 49 ? 7 * s + j : 0, 64);
-    if (lane < 49 && s > j && r >= s) a -= lrj * lsj;
+#pragma unroll
+  for (int i = 0; i < 7; ++i) {
+#pragma unroll
+    for (int k = 0; k <= i; ++k) {
+      double v = D[7 * i + k];
+#pragma unroll
+      for (int q = 0; q < k; ++q) v -= L[i][q] * L[k][q];
+      if (k == i) {
+        ok = ok && v > 0.0;
+        L[i][i] = sqrt(v > 0.0 ? v : 1.0);
+        rinv[i] = 1.0 / L[i][i];
+      } else {
+        L[i][k] = v * rinv[k];
+      }
+    }
   }
-  if (lane < 49) D[lane] = s > r ? 0.0 : a;
+#pragma unroll
+  for (int i = 0; i < 7; ++i)
+#pragma unroll
+    for (int k = 0; k < 7; ++k) D[7 * i + k] = k <= i ? L[i][k] : 0.0;
+  // column j of L^{-1} by forward substitution against e_j
+#pragma unroll
+  for (int j = 0; j < 7; ++j) {
+    double v[7];
+#pragma unroll
+    for (int i = 0; i < 7; ++i) {
+      if (i < j) {
+        v[i] = 0.0;
+      } else if (i == j) {
+        v[i] = rinv[j];
+      } else {
+        double t = 0.0;
+#pragma unroll
+        for (int k = j; k < i; ++k) t += L[i][k] * v[k];
+        v[i] = -t * rinv[i];
+      }
+      Di[7 * i + j] = v[i];
+      if (copy) copy[7 * i + j] = v[i];
+    }
+  }
   return ok;
 }
 
-// One row of L_ij = S_ij L_jj^{-T} (forward substitution against the diagonal
-// factor D), in place; optionally copied to `copy` as well.
-__device__ inline void trsm_row(double* row, const double* D, double* copy) {
-  double y[7];
+// One row of L_ij = S_ij L_jj^{-T} in place, with Dinv = L_jj^{-1}; optionally
+// copied to `copy` as well.
+__device__ inline void trsm_row(double* row, const double* Dinv, double* copy) {
+  double x[7], y[7];
+#pragma unroll
+  for (int k = 0; k < 7; ++k) x[k] = row[k];
+#pragma unroll
   for (int j = 0; j < 7; ++j) {
-    double v = row[j];
-    for (int k = 0; k < j; ++k) v -= y[k] * D[7 * j + k];
-    y[j] = v / D[8 * j];
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k <= j; ++k) v += x[k] * Dinv[7 * j + k];
+    y[j] = v;
   }
+#pragma unroll
   for (int j = 0; j < 7; ++j) row[j] = y[j];
   if (copy)
+#pragma unroll
     for (int j = 0; j < 7; ++j) copy[j] = y[j];
 }
 
@@ -324,9 +361,10 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
       }
     }
     __syncthreads();
-    // (B) Cholesky of each diagonal block of the level: one wavefront per block
-    for (int cc = c0 + wv; cc < c1; cc += PGO_WG / 64) {
-      if (!chol7_wave(d.Ld + 49 * d.flev_col[cc], lane) && lane == 0) s_fail = 1;
+    // (B) Cholesky of each diagonal block of the level (and its inverse): one lane per block
+    for (int cc = c0 + tid; cc < c1; cc += PGO_WG) {
+      const int col = d.flev_col[cc];
+      if (!chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, nullptr)) s_fail = 1;
     }
     __syncthreads();
     if (s_fail) break;
@@ -335,7 +373,7 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
       const int b0 = d.lb_ptr[l], nb = d.lb_ptr[l + 1] - b0;
       for (int x = tid; x < nb * 7; x += PGO_WG) {
         const int bb = d.lb_blk[b0 + x / 7];
-        trsm_row(d.Lb + 49 * bb + 7 * (x % 7), d.Ld + 49 * d.blk_col[bb], nullptr);
+        trsm_row(d.Lb + 49 * bb + 7 * (x % 7), d.Di + 49 * d.blk_col[bb], nullptr);
       }
     }
     __syncthreads();
@@ -358,6 +396,7 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
   __shared__ double sh[PGO_WG / 64 + 1];
   __shared__ int s_fail;
   __shared__ double panel[49 * (PGO_KMAX - 1)];  // the clique column being applied
+  __shared__ double dinv[49];                     // inverse of its diagonal block
   const int tid = threadIdx.x;
   if (*d.status != 0) return;
   if (tid == 0) s_fail = 0;
@@ -371,44 +410,76 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
     const int K = d.K;
     for (int j = 0; j < K; ++j) {
       const int c = d.p0 + j;
-      if (wv == 0 && !chol7_wave(d.Ld + 49 * c, lane) && lane == 0) s_fail = 1;
+      if (tid == 0 && !chol7_lane(d.Ld + 49 * c, d.Di + 49 * c, dinv)) s_fail = 1;
       __syncthreads();
       if (s_fail) break;
       const int nrow = K - 1 - j;
       for (int x = tid; x < nrow * 7; x += PGO_WG) {
         const int i = j + 1 + x / 7;
-        trsm_row(d.Lb + 49 * clique_block(d, i, j) + 7 * (x % 7), d.Ld + 49 * c, panel + 49 * (i - j - 1) + 7 * (x % 7));
+        trsm_row(d.Lb + 49 * clique_block(d, i, j) + 7 * (x % 7), dinv, panel + 49 * (i - j - 1) + 7 * (x % 7));
       }
       __syncthreads();
-      const int nt = nrow * (nrow + 1) / 2;
-      const int r = lane < 49 ? lane / 7 : 0, sc = lane < 49 ? lane % 7 : 0;
-      // eight targets per wavefront at a time: their loads are issued before any store
-      constexpr int NB = 8;
-      for (int tb = wv * NB; tb < nt; tb += (PGO_WG / 64) * NB) {
-        double* dst[NB];
-        double old[NB];
-        int ia[NB], ib[NB];
+      // trailing blocks in 2x2 tiles (rows 2A, 2A+1 against columns 2B, 2B+1, B <= A):
+      // each lane keeps the four panel rows it needs in registers, so a tile costs
+      // 28 LDS reads for 4 blocks. The next tile's old values are loaded (always, from
+      // valid blocks) before this tile is computed and stored, so no tile waits for the
+      // previous tile's stores.
+      const int r = lane < 49 ? lane / 7 : 0, sc = lane < 49 ? lane % 7 : 0, el = lane < 49 ? lane : 48;
+      const int nA = (nrow + 1) / 2, ntile = nA * (nA + 1) / 2;
+      auto tile_blocks = [&](int ti, int& A, int& B, double* (&dst)[4], bool (&use)[4]) {
+        A = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
+        A -= (A * (A + 1) / 2 > ti) ? 1 : 0;
+        A += ((A + 1) * (A + 2) / 2 <= ti) ? 1 : 0;
+        B = ti - A * (A + 1) / 2;
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const int ti = tb + q < nt ? tb + q : nt - 1;
-          // ti -> (a, b), 0 <= b <= a < nrow, row-major over the lower triangle
-          int a = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
-          a -= (a * (a + 1) / 2 > ti) ? 1 : 0;
-          a += ((a + 1) * (a + 2) / 2 <= ti) ? 1 : 0;
-          ia[q] = a;
-          ib[q] = ti - a * (a + 1) / 2;
-          const int i = j + 1 + ia[q], i2 = j + 1 + ib[q];
-          dst[q] = (i == i2) ? d.Ld + 49 * (d.p0 + i) : d.Lb + 49 * clique_block(d, i, i2);
-          old[q] = lane < 49 ? dst[q][lane] : 0.0;
+        for (int q = 0; q < 4; ++q) {
+          const int a_ = 2 * A + (q >> 1), b_ = 2 * B + (q & 1);
+          use[q] = a_ < nrow && b_ <= a_;
+          const int i = j + 1 + (use[q] ? a_ : 0), i2 = j + 1 + (use[q] ? b_ : 0);
+          dst[q] = ((i == i2) ? d.Ld + 49 * (d.p0 + i) : d.Lb + 49 * clique_block(d, i, i2)) + el;
+        }
+      };
+      int A, B;
+      double* dst[4];
+      bool use[4];
+      double old[4];
+      if (wv < ntile) {
+        tile_blocks(wv, A, B, dst, use);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) old[q] = *dst[q];
+      }
+      for (int ti = wv; ti < ntile; ti += PGO_WG / 64) {
+        int An, Bn;
+        double* dstn[4];
+        bool usen[4];
+        double oldn[4];
+        tile_blocks(ti + PGO_WG / 64 < ntile ? ti + PGO_WG / 64 : ti, An, Bn, dstn, usen);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) oldn[q] = *dstn[q];
+        double pa[2][7], pb[2][7];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int ra = min(2 * A + h, nrow - 1), rb = min(2 * B + h, nrow - 1);
+#pragma unroll
+          for (int u = 0; u < 7; ++u) {
+            pa[h][u] = panel[49 * ra + 7 * r + u];
+            pb[h][u] = panel[49 * rb + 7 * sc + u];
+          }
         }
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
-          const double* Pa = panel + 49 * ia[q] + 7 * r;
-          const double* Pb = panel + 49 * ib[q] + 7 * sc;
+        for (int q = 0; q < 4; ++q) {
           double acc = 0.0;
 #pragma unroll
-          for (int u = 0; u < 7; ++u) acc += Pa[u] * Pb[u];
-          if (lane < 49 && tb + q < nt) dst[q][lane] = old[q] - acc;
+          for (int u = 0; u < 7; ++u) acc += pa[q >> 1][u] * pb[q & 1][u];
+          if (use[q] && lane < 49) *dst[q] = old[q] - acc;
+        }
+        A = An;
+        B = Bn;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          dst[q] = dstn[q];
+          use[q] = usen[q];
+          old[q] = oldn[q];
         }
       }
       __syncthreads();
@@ -430,17 +501,20 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
         for (int r = 0; r < 7; ++r)
           for (int u = 0; u < 7; ++u) acc[r] += L[7 * r + u] * y[u];
       }
-      for (int r = 0; r < 7; ++r) acc[r] = wave_sum(acc[r]);
-      if (lane == 0) {
-        const double* D = d.Ld + 49 * c;
+      wave_totals_f64(acc);
+      if (lane == 0) {  // y_c = L_cc^{-1} (y_c - acc)
+        const double* Di = d.Di + 49 * c;
         double* y = d.g + 7 * c;
-        double t[7];
+        double v[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) v[r] = y[r] - acc[r];
+#pragma unroll
         for (int r = 0; r < 7; ++r) {
-          double v = y[r] - acc[r];
-          for (int k = 0; k < r; ++k) v -= D[7 * r + k] * t[k];
-          t[r] = v / D[8 * r];
+          double t = 0.0;
+#pragma unroll
+          for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
+          y[r] = t;
         }
-        for (int r = 0; r < 7; ++r) y[r] = t[r];
       }
     }
     __syncthreads();
@@ -456,17 +530,20 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
         for (int r = 0; r < 7; ++r)
           for (int u = 0; u < 7; ++u) acc[u] += L[7 * r + u] * x[r];
       }
-      for (int r = 0; r < 7; ++r) acc[r] = wave_sum(acc[r]);
-      if (lane == 0) {
-        const double* D = d.Ld + 49 * c;
+      wave_totals_f64(acc);
+      if (lane == 0) {  // x_c = L_cc^{-T} (x_c - acc)
+        const double* Di = d.Di + 49 * c;
         double* x = d.g + 7 * c;
-        double t[7];
-        for (int r = 6; r >= 0; --r) {
-          double v = x[r] - acc[r];
-          for (int k = r + 1; k < 7; ++k) v -= D[7 * k + r] * t[k];
-          t[r] = v / D[8 * r];
+        double v[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) v[r] = x[r] - acc[r];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = r; k < 7; ++k) t += Di[7 * k + r] * v[k];
+          x[r] = t;
         }
-        for (int r = 0; r < 7; ++r) x[r] = t[r];
       }
     }
     __syncthreads();
@@ -937,7 +1014,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.chain.size() + 4);
-    total += bytes_of<double>(49 * (size_t)m) + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
+    total += bytes_of<double>(49 * (size_t)m) * 2 + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<double>(iters_cap) + bytes_of<int32_t>(4);
     total += bytes_of<double>(7 * (size_t)m + 7) * 2 + bytes_of<double>(8);  // LM: gsave, dsave, pred
@@ -996,6 +1073,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
     d.n_chain = (int32_t)(S.chain.size() / 4);
     d.Ld = carve<double>(c, 49 * (size_t)m);
+    d.Di = carve<double>(c, 49 * (size_t)m);
     d.Lb = carve<double>(c, 49 * (size_t)nb + 49);
     d.g = carve<double>(c, 7 * (size_t)m + 7);
     d.M = carve<double>(c, 49 * (size_t)E + 49);
