@@ -35,7 +35,6 @@ namespace s3a {
 struct PgoDev {
   int32_t n_nodes, n_edges, m, gauge;   // m = free nodes
   int32_t nblk;                         // off-diagonal factor blocks
-  int32_t nlev;
   const int32_t* ei;                    // [E] node i
   const int32_t* ej;                    // [E] node j
   const int32_t* pos;                   // [n] node -> elimination position (-1: gauge)
@@ -52,26 +51,33 @@ struct PgoDev {
   // updates: target t (0..m-1 diagonal of position t, m + b off-diagonal block b) gets
   // -= L_a L_b^T for (a, b) in up_a/up_b[up_ptr[t]..]; a, b index blocks (always off-diagonal)
   const int32_t* up_ptr; const int32_t* up_a; const int32_t* up_b;
-  // solve schedule: every column, by level from the leaves
-  const int32_t* lev_ptr; const int32_t* lev_col;
-  // factor schedule of the sparse part (columns below p0): per level its columns, the
-  // flattened update targets (diagonal c or m + off-diagonal block) and off-diagonal blocks
+  // schedule of the sparse part (columns below p0), for the factorisation and both
+  // solves: per level its columns, the update targets that receive updates (diagonal
+  // c or m + off-diagonal block) and the off-diagonal blocks; for the column at
+  // schedule position j, its row blocks fs_blk[fs_ptr[j]..] (forward solve) and its
+  // column blocks bs_blk[bs_ptr[j]..] (backward solve), consecutive over a level
   int32_t nflev;
   const int32_t* flev_ptr; const int32_t* flev_col;
+  const int32_t* fs_ptr; const int32_t* fs_blk;
+  const int32_t* bs_ptr; const int32_t* bs_blk;
   const int32_t* lt_ptr; const int32_t* lt_tgt;
   const int32_t* lb_ptr; const int32_t* lb_blk;
   // dense trailing clique: columns p0 .. m-1 (K of them) hold every block below the
-  // diagonal (block of rows p0+i, column p0+k at clique_block(i, k)); the clique's
-  // targets get the updates of sparse columns (dt lists) before the dense factorisation
-  int32_t K, p0, cp0, n_dt;  // cp0: first block of column p0
+  // diagonal. Its blocks, with the updates of the sparse columns applied (dt lists),
+  // form the dense front F (order nF = 7 K padded with identity to a multiple of the
+  // update tile, column-major, lower triangle), factored in place; Finv holds the
+  // inverses of the front's FB x FB diagonal blocks (row-major) for the solves.
+  int32_t K, p0, n_dt, nF;
   const int32_t* dt_tgt; const int32_t* dt_ptr; const int32_t* dup_a; const int32_t* dup_b;
-  // rows of L for the forward solve: blocks (c, k), k < c
+  double* F;
+  double* Finv;
+  // rows of L: blocks (c, k), k < c (the clique rows' right-hand side)
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
   const int32_t* chain; int32_t n_chain;
   // numeric storage
   double* Ld;     // [m][49] diagonal blocks (lower Cholesky factor after factorisation)
-  double* Di;     // [m][49] inverses of the factored diagonal blocks (lower triangular)
+  double* Di;     // [m][49] inverses of the factored diagonal blocks of the sparse columns
   double* Lb;     // [nblk][49]
   double* g;      // [m][7]  gradient, then solution
   double* M;      // [E][49] per-edge psi A^T Omega A
@@ -164,7 +170,8 @@ __global__ __launch_bounds__(128) void k_pgo_linearize(PgoDev d, const s3a_sim3*
 
 constexpr int PGO_WG = 1024;
 
-// Deterministic workgroup sum of per-lane doubles (fixed tree).
+// Deterministic workgroup sum of per-lane doubles (fixed tree) over WG threads.
+template <int WG>
 __device__ inline double wg_sum(double v, double* sh) {
   v = wave_sum(v);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -172,29 +179,42 @@ __device__ inline double wg_sum(double v, double* sh) {
   __syncthreads();
   double s = 0.0;
   if (threadIdx.x == 0) {
-    for (int q = 0; q < PGO_WG / 64; ++q) s += sh[q];
-    sh[PGO_WG / 64] = s;
+    for (int q = 0; q < WG / 64; ++q) s += sh[q];
+    sh[WG / 64] = s;
   }
   __syncthreads();
-  s = sh[PGO_WG / 64];
+  s = sh[WG / 64];
   __syncthreads();
   return s;
 }
 
-// One Gauss-Newton iteration on one workgroup: chi^2, assembly, factorisation,
-// solves, update. `it` indexes the chi^2 record.
-// Largest dense clique factored by the right-looking step (its column panel lives in LDS).
-constexpr int PGO_KMAX = 96;
+// Dense front of the trailing clique: at most PGO_KMAX node columns; panels of FB
+// columns, trailing updates in FT x FT tiles, one workgroup of FRONT_WG threads.
+constexpr int PGO_KMAX = 72;
+constexpr int FB = 32;
+constexpr int FT = 64;
+constexpr int FRONT_MAX = 512;
+constexpr int FRONT_WG = 512;
+static_assert((7 * PGO_KMAX + FT - 1) / FT * FT <= FRONT_MAX, "front order");
+constexpr int FIN_WG = 512;  // solves: 256 registers per lane
+static_assert(FIN_WG % FB == 0 && (FIN_WG / FB) <= 64 && ((FIN_WG / FB) & (FIN_WG / FB - 1)) == 0, "row slots per front column");
+static_assert(FRONT_MAX - FB <= FRONT_WG, "one panel row per thread");
+
+// Element `lane` of factor block `target` (diagonal c, or m + off-diagonal block).
+__device__ inline double* target_elem(const PgoDev& d, int target, int lane) {
+  const int e = lane < 49 ? lane : 0;
+  return target < d.m ? d.Ld + 49 * target + e : d.Lb + 49 * (target - d.m) + e;
+}
 
 // S -= sum_q L_a L_b^T over one target's update list [q0, q1) (blocks a = ua[q], b = ub[q]),
 // by one wavefront, lane = element (r, s) of the 7x7 block, in list order. The block
 // indices are fetched 64 at a time, one per lane, and read back from lanes (uniform),
 // so the only dependent loads left are the blocks; four updates are in flight.
-__device__ inline void update_target(const PgoDev& d, int target, int q0, int q1, const int32_t* ua,
-                                     const int32_t* ub, int lane) {
+// The lane's element is read from `src` and the result written to `dst`.
+__device__ inline void update_target(const PgoDev& d, const double* src, double* dst, int q0, int q1,
+                                     const int32_t* ua, const int32_t* ub, int lane) {
   const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
-  double* dst = target < d.m ? d.Ld + 49 * target + (lane < 49 ? lane : 0) : d.Lb + 49 * (target - d.m) + (lane < 49 ? lane : 0);
-  const double old = *dst;  // issued first: its latency overlaps the update loads
+  const double old = *src;  // issued first: its latency overlaps the update loads
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
   for (int qb = q0; qb < q1; qb += 64) {
     const int nq = min(64, q1 - qb);
@@ -299,12 +319,6 @@ __device__ inline void trsm_row(double* row, const double* Dinv, double* copy) {
     for (int j = 0; j < 7; ++j) copy[j] = y[j];
 }
 
-// Clique block (i, k), i > k (clique-local indices): column p0 + k holds every row
-// below it, in order, right after the blocks of the clique's earlier columns.
-__device__ inline int clique_block(const PgoDev& d, int i, int k) {
-  return d.cp0 + k * (d.K - 1) - k * (k - 1) / 2 + (i - k - 1);
-}
-
 // Assembly of the normal equations from the per-edge linearisations:
 // independent sums, spread over the whole chip.
 __global__ __launch_bounds__(256) void k_pgo_assemble(PgoDev d, double lambda, int lm) {
@@ -343,7 +357,7 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
   if (*d.status != 0) return;
   double part = 0.0;
   for (int k = tid; k < d.n_edges; k += PGO_WG) part += d.r2[k];
-  const double c2 = wg_sum(part, sh);  // fixed order
+  const double c2 = wg_sum<PGO_WG>(part, sh);  // fixed order
   if (tid == 0) d.chi2[it] = c2;
   if (!update) return;
   if (tid == 0) s_fail = 0;
@@ -357,7 +371,8 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
       const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
       for (int ti = wv; ti < nt; ti += PGO_WG / 64) {
         const int target = d.lt_tgt[t0 + ti];
-        update_target(d, target, d.up_ptr[target], d.up_ptr[target + 1], d.up_a, d.up_b, lane);
+        double* e = target_elem(d, target, lane);
+        update_target(d, e, e, d.up_ptr[target], d.up_ptr[target + 1], d.up_a, d.up_b, lane);
       }
     }
     __syncthreads();
@@ -381,182 +396,319 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
   if (s_fail && tid == 0) *d.status = 2;
 }
 
-// The sparse columns' updates of every block of the clique: independent targets,
-// one wavefront each, spread over the whole chip.
+// The clique's blocks with the sparse columns' updates applied, written into the
+// dense front: independent targets, one wavefront each, spread over the whole chip.
 __global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
   if (*d.status != 0) return;
   const int ti = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
   if (ti >= d.n_dt) return;
-  update_target(d, d.dt_tgt[ti], d.dt_ptr[ti], d.dt_ptr[ti + 1], d.dup_a, d.dup_b, lane);
+  const int t = d.dt_tgt[ti];
+  const int row = t < d.m ? t : d.blk_row[t - d.m], col = t < d.m ? t : d.blk_col[t - d.m];
+  const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
+  double* dst = d.F + (size_t)(7 * (col - d.p0) + s) * d.nF + 7 * (row - d.p0) + r;
+  update_target(d, target_elem(d, t, lane), dst, d.dt_ptr[ti], d.dt_ptr[ti + 1], d.dup_a, d.dup_b, lane);
 }
 
-// The clique's right-looking factorisation, the two triangular solves and the
-// update T <- Exp(dx) T, by one workgroup.
-__global__ __launch_bounds__(PGO_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, double lambda, int lm) {
-  __shared__ double sh[PGO_WG / 64 + 1];
+// Identity padding of the front (rows and columns 7 K .. nF-1), zeros elsewhere.
+__global__ __launch_bounds__(256) void k_pgo_front_init(PgoDev d) {
+  const size_t n = (size_t)d.nF, x = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= n * n) return;
+  const size_t r = x % n, c = x / n;
+  d.F[x] = (r == c && r >= (size_t)(7 * d.K)) ? 1.0 : 0.0;
+}
+
+__device__ inline double readlane_f64(double x, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Right-looking blocked Cholesky of the front F (order nF, column-major, lower
+// triangle) in place, by one workgroup, panel by panel of FB columns:
+//  (1) the FB x FB diagonal block by one wavefront, lane = row, the pivot column
+//      read across lanes; its factor also goes to LDS, with the reciprocal pivots;
+//  (2) the rows below: L_i = A_i L_kk^{-T} by forward substitution, one row per
+//      thread, written to F and to an LDS copy of the panel (column-major by row);
+//      one wavefront meanwhile inverts L_kk for the triangular solves;
+//  (3) the trailing lower triangle A -= P P^T in FT x FT tiles, one wavefront per
+//      tile, an 8 x 8 register block per lane, the panel read from LDS.
+__global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
+  __shared__ double P[FB * FRONT_MAX];  // panel: P[k * FRONT_MAX + i], i = row - (k0 + FB)
+  __shared__ double Ls[FB * FB];        // diagonal factor, row-major, zero above the diagonal
+  __shared__ double rinv[FB];
   __shared__ int s_fail;
-  __shared__ double panel[49 * (PGO_KMAX - 1)];  // the clique column being applied
-  __shared__ double dinv[49];                     // inverse of its diagonal block
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   if (*d.status != 0) return;
   if (tid == 0) s_fail = 0;
-  __syncthreads();
-  const int lane = tid & 63, wv = tid >> 6;
-  if (d.K > 0) {
-    // (D2) right-looking over the clique, one node column j at a time: factor the
-    // diagonal block, solve the column's blocks (kept in LDS as well), then update
-    // every trailing block (i, i'), j < i' <= i, by L_ij L_i'j^T: one wavefront per
-    // block, lane = element.
-    const int K = d.K;
-    for (int j = 0; j < K; ++j) {
-      const int c = d.p0 + j;
-      if (tid == 0 && !chol7_lane(d.Ld + 49 * c, d.Di + 49 * c, dinv)) s_fail = 1;
-      __syncthreads();
-      if (s_fail) break;
-      const int nrow = K - 1 - j;
-      for (int x = tid; x < nrow * 7; x += PGO_WG) {
-        const int i = j + 1 + x / 7;
-        trsm_row(d.Lb + 49 * clique_block(d, i, j) + 7 * (x % 7), dinv, panel + 49 * (i - j - 1) + 7 * (x % 7));
+  const int n = d.nF;
+  double* F = d.F;
+  for (int k0 = 0; k0 < n; k0 += FB) {
+    // (1)
+    if (wv == 0) {
+      const int r = lane < FB ? lane : FB - 1;
+      double a[FB];
+#pragma unroll
+      for (int c = 0; c < FB; ++c) a[c] = F[(size_t)(k0 + c) * n + k0 + (c <= r ? r : c)];
+#pragma unroll
+      for (int c = 0; c < FB; ++c) a[c] = c <= r ? a[c] : 0.0;
+      bool ok = true;
+      double rv = 1.0;
+#pragma unroll
+      for (int k = 0; k < FB; ++k) {
+        const double dkk = readlane_f64(a[k], k);
+        ok = ok && dkk > 0.0;
+        const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0), rk = 1.0 / lkk;
+        a[k] = lane == k ? lkk : a[k] * rk;
+        rv = lane == k ? rk : rv;
+        // rows above j pick up values above the diagonal here; they are never read
+#pragma unroll
+        for (int j = k + 1; j < FB; ++j) a[j] -= a[k] * readlane_f64(a[k], j);
+      }
+      if (lane < FB) {
+#pragma unroll
+        for (int c = 0; c < FB; ++c) {
+          if (c <= lane) F[(size_t)(k0 + c) * n + k0 + lane] = a[c];
+          Ls[lane * FB + c] = c <= lane ? a[c] : 0.0;
+        }
+        rinv[lane] = rv;
+      }
+      if (!ok && lane == 0) s_fail = 1;
+    }
+    __syncthreads();
+    if (s_fail) break;
+    // (2)
+    const int s0 = k0 + FB, nr = n - s0;
+    if (tid < nr) {  // nr < FRONT_WG: one row per thread
+      double x[FB];
+#pragma unroll
+      for (int c = 0; c < FB; ++c) x[c] = F[(size_t)(k0 + c) * n + s0 + tid];
+#pragma unroll
+      for (int c = 0; c < FB; ++c) {
+        double v = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) v -= x[k] * Ls[c * FB + k];
+        x[c] = v * rinv[c];
+      }
+#pragma unroll
+      for (int c = 0; c < FB; ++c) {
+        F[(size_t)(k0 + c) * n + s0 + tid] = x[c];
+        P[c * FRONT_MAX + tid] = x[c];
+      }
+    }
+    if (wv == FRONT_WG / 64 - 1 && lane < FB) {
+      // column `lane` of L_kk^{-1}: forward substitution against e_lane
+      double v[FB];
+#pragma unroll
+      for (int r = 0; r < FB; ++r) {
+        double t = r == lane ? 1.0 : 0.0;
+#pragma unroll
+        for (int k = 0; k < r; ++k) t -= Ls[r * FB + k] * v[k];
+        v[r] = t * rinv[r];
+      }
+      double* Vi = d.Finv + (size_t)(k0 / FB) * FB * FB;
+#pragma unroll
+      for (int r = 0; r < FB; ++r) Vi[r * FB + lane] = v[r];
+    }
+    __syncthreads();
+    // (3)
+    const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
+    const int lr = lane >> 3, lc = lane & 7;
+    for (int ti = wv; ti < ntile; ti += FRONT_WG / 64) {
+      int I = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
+      I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
+      I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
+      const int J = ti - I * (I + 1) / 2;
+      const int r0 = FT * I + 8 * lr, c0 = FT * J + 8 * lc;  // relative to s0; nr is a multiple of 8
+      const bool in = r0 < nr && c0 < nr;
+      double* blk = F + (in ? (size_t)(s0 + c0) * n + s0 + r0 : 0);
+      double acc[8][8];
+#pragma unroll
+      for (int v = 0; v < 8; ++v)
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[u][v] = blk[(size_t)v * n + u];
+#pragma unroll 4
+      for (int k = 0; k < FB; ++k) {
+        double pa[8], pb[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          pa[u] = P[k * FRONT_MAX + r0 + u];
+          pb[u] = P[k * FRONT_MAX + c0 + u];
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[u][v] -= pa[u] * pb[v];
+      }
+      if (in) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+            if (I != J || r0 + u >= c0 + v) blk[(size_t)v * n + u] = acc[u][v];
+      }
+    }
+    __syncthreads();
+  }
+  if (s_fail && tid == 0) *d.status = 2;
+}
+
+// Products of one solve level kept in LDS at a time.
+constexpr int SOLVE_CHUNK = 1024;
+
+// One level of a sparse triangular solve, by the workgroup. Forward: for each
+// column c of the level, y_c = L_cc^{-1} (y_c - sum_k L_ck y_k) over its row
+// blocks; backward: x_c = L_cc^{-T} (x_c - sum_i L_ic^T x_i) over its column
+// blocks. Every block product of the level is formed in parallel (one thread per
+// block, into LDS), then one thread per column sums its own products in list order.
+template <bool backward>
+__device__ inline void solve_level(const PgoDev& d, int l, double* prod) {
+  const int tid = threadIdx.x;
+  const int32_t* ptr = backward ? d.bs_ptr : d.fs_ptr;
+  const int32_t* blk = backward ? d.bs_blk : d.fs_blk;
+  const int j0 = d.flev_ptr[l], j1 = d.flev_ptr[l + 1];
+  for (int jb = j0; jb < j1; jb += FIN_WG) {
+    const int j = jb + tid;
+    const bool own = j < j1;
+    const int c = own ? d.flev_col[j] : 0;
+    const int p_lo = own ? ptr[j] : 0, p_hi = own ? ptr[j + 1] : 0;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    const int q_lo = ptr[jb], q_hi = ptr[min(jb + FIN_WG, j1)];
+    for (int base = q_lo; base < q_hi; base += SOLVE_CHUNK) {
+      const int top = min(base + SOLVE_CHUNK, q_hi);
+      for (int q = base + tid; q < top; q += FIN_WG) {
+        const int b = blk[q];
+        const double* L = d.Lb + 49 * b;
+        const double* x = d.g + 7 * (backward ? d.blk_row[b] : d.blk_col[b]);
+        double xv[7];
+#pragma unroll
+        for (int u = 0; u < 7; ++u) xv[u] = x[u];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int u = 0; u < 7; ++u) t += (backward ? L[7 * u + r] : L[7 * r + u]) * xv[u];
+          prod[7 * (q - base) + r] = t;
+        }
       }
       __syncthreads();
-      // trailing blocks in 2x2 tiles (rows 2A, 2A+1 against columns 2B, 2B+1, B <= A):
-      // each lane keeps the four panel rows it needs in registers, so a tile costs
-      // 28 LDS reads for 4 blocks. The next tile's old values are loaded (always, from
-      // valid blocks) before this tile is computed and stored, so no tile waits for the
-      // previous tile's stores.
-      const int r = lane < 49 ? lane / 7 : 0, sc = lane < 49 ? lane % 7 : 0, el = lane < 49 ? lane : 48;
-      const int nA = (nrow + 1) / 2, ntile = nA * (nA + 1) / 2;
-      auto tile_blocks = [&](int ti, int& A, int& B, double* (&dst)[4], bool (&use)[4]) {
-        A = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
-        A -= (A * (A + 1) / 2 > ti) ? 1 : 0;
-        A += ((A + 1) * (A + 2) / 2 <= ti) ? 1 : 0;
-        B = ti - A * (A + 1) / 2;
+      for (int q = max(p_lo, base); q < min(p_hi, top); ++q)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int a_ = 2 * A + (q >> 1), b_ = 2 * B + (q & 1);
-          use[q] = a_ < nrow && b_ <= a_;
-          const int i = j + 1 + (use[q] ? a_ : 0), i2 = j + 1 + (use[q] ? b_ : 0);
-          dst[q] = ((i == i2) ? d.Ld + 49 * (d.p0 + i) : d.Lb + 49 * clique_block(d, i, i2)) + el;
-        }
-      };
-      int A, B;
-      double* dst[4];
-      bool use[4];
-      double old[4];
-      if (wv < ntile) {
-        tile_blocks(wv, A, B, dst, use);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) old[q] = *dst[q];
-      }
-      for (int ti = wv; ti < ntile; ti += PGO_WG / 64) {
-        int An, Bn;
-        double* dstn[4];
-        bool usen[4];
-        double oldn[4];
-        tile_blocks(ti + PGO_WG / 64 < ntile ? ti + PGO_WG / 64 : ti, An, Bn, dstn, usen);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) oldn[q] = *dstn[q];
-        double pa[2][7], pb[2][7];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int ra = min(2 * A + h, nrow - 1), rb = min(2 * B + h, nrow - 1);
-#pragma unroll
-          for (int u = 0; u < 7; ++u) {
-            pa[h][u] = panel[49 * ra + 7 * r + u];
-            pb[h][u] = panel[49 * rb + 7 * sc + u];
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          double acc = 0.0;
-#pragma unroll
-          for (int u = 0; u < 7; ++u) acc += pa[q >> 1][u] * pb[q & 1][u];
-          if (use[q] && lane < 49) *dst[q] = old[q] - acc;
-        }
-        A = An;
-        B = Bn;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          dst[q] = dstn[q];
-          use[q] = usen[q];
-          old[q] = oldn[q];
-        }
-      }
+        for (int r = 0; r < 7; ++r) acc[r] += prod[7 * (q - base) + r];
       __syncthreads();
     }
+    if (own) {
+      const double* Di = d.Di + 49 * c;
+      double* y = d.g + 7 * c;
+      double v[7];
+#pragma unroll
+      for (int r = 0; r < 7; ++r) v[r] = y[r] - acc[r];
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        double t = 0.0;
+        if constexpr (backward) {
+#pragma unroll
+          for (int k = r; k < 7; ++k) t += Di[7 * k + r] * v[k];
+        } else {
+#pragma unroll
+          for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
+        }
+        y[r] = t;
+      }
+    }
   }
-  if (s_fail) {
-    if (tid == 0) *d.status = 2;
-    return;
-  }
-  // ---- forward solve L y = -g, levels from the leaves; one wavefront per column
-  for (int l = 0; l < d.nlev; ++l) {
-    for (int cc = d.lev_ptr[l] + wv; cc < d.lev_ptr[l + 1]; cc += PGO_WG / 64) {
-      const int c = d.lev_col[cc];
+  __syncthreads();
+}
+
+// The two triangular solves and the update T <- Exp(dx) T, by one workgroup:
+// forward over the sparse columns level by level, the clique rows' right-hand
+// side, forward and backward through the factored front (its part of the vector
+// in LDS), backward over the sparse columns from the root.
+__global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, double lambda, int lm) {
+  __shared__ double sh[FIN_WG / 64 + 1];
+  __shared__ double ys[FRONT_MAX];
+  __shared__ double red[FB];
+  __shared__ double prod[7 * SOLVE_CHUNK];
+  const int tid = threadIdx.x;
+  if (*d.status != 0) return;
+  const int lane = tid & 63, wv = tid >> 6;
+  // ---- forward solve L y = -g over the sparse columns, levels from the leaves
+  for (int l = 0; l < d.nflev; ++l) solve_level<false>(d, l, prod);
+  if (d.K > 0) {
+    const int n = d.nF, nK = 7 * d.K;
+    // ---- the clique rows: y_i - sum over sparse columns k of L_ik y_k, into LDS
+    for (int i = wv; i < d.K; i += FIN_WG / 64) {
+      const int c = d.p0 + i;
       double acc[7] = {0, 0, 0, 0, 0, 0, 0};
       for (int q = d.row_ptr[c] + lane; q < d.row_ptr[c + 1]; q += 64) {
         const int b = d.row_blk[q];
+        const int k = d.blk_col[b];
+        if (k >= d.p0) continue;
         const double* L = d.Lb + 49 * b;
-        const double* y = d.g + 7 * d.blk_col[b];
+        const double* y = d.g + 7 * k;
         for (int r = 0; r < 7; ++r)
           for (int u = 0; u < 7; ++u) acc[r] += L[7 * r + u] * y[u];
       }
       wave_totals_f64(acc);
-      if (lane == 0) {  // y_c = L_cc^{-1} (y_c - acc)
-        const double* Di = d.Di + 49 * c;
-        double* y = d.g + 7 * c;
-        double v[7];
+      if (lane == 0)
 #pragma unroll
-        for (int r = 0; r < 7; ++r) v[r] = y[r] - acc[r];
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-          double t = 0.0;
-#pragma unroll
-          for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
-          y[r] = t;
-        }
-      }
+        for (int r = 0; r < 7; ++r) ys[7 * i + r] = d.g[7 * c + r] - acc[r];
     }
+    for (int x = nK + tid; x < n; x += FIN_WG) ys[x] = 0.0;
+    __syncthreads();
+    // ---- forward through the front: y_blk = L_blk^{-1} y_blk, then the rows below
+    for (int k0 = 0; k0 < n; k0 += FB) {
+      if (tid < FB) {
+        const double* Vi = d.Finv + (size_t)(k0 / FB) * FB * FB + tid * FB;
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < FB; ++c) t += Vi[c] * ys[k0 + c];
+        ys[k0 + tid] = t;  // one wavefront: every lane's reads precede the writes
+      }
+      __syncthreads();
+      for (int i = k0 + FB + tid; i < n; i += FIN_WG) {
+        double t = 0.0;
+#pragma unroll
+        for (int c = 0; c < FB; ++c) t += d.F[(size_t)(k0 + c) * n + i] * ys[k0 + c];
+        ys[i] -= t;
+      }
+      __syncthreads();
+    }
+    // ---- backward through the front: x_blk = L_blk^{-T} (y_blk - sum of L_ib^T x_i below)
+    for (int k0 = n - FB; k0 >= 0; k0 -= FB) {
+      {
+        constexpr int SL = FIN_WG / FB;  // row slots per column
+        const int c = tid / SL, q = tid % SL;
+        double t = 0.0;
+        for (int i = k0 + FB + q; i < n; i += SL) t += d.F[(size_t)(k0 + c) * n + i] * ys[i];
+#pragma unroll
+        for (int o = SL / 2; o > 0; o >>= 1) t += __shfl_xor(t, o, 64);
+        if (q == 0) red[c] = t;
+      }
+      __syncthreads();
+      if (tid < FB) {
+        const double* Vi = d.Finv + (size_t)(k0 / FB) * FB * FB;
+        double t = 0.0;
+#pragma unroll
+        for (int r = 0; r < FB; ++r) t += Vi[r * FB + tid] * (ys[k0 + r] - red[r]);
+        ys[k0 + tid] = t;  // one wavefront: every lane's reads precede the writes
+      }
+      __syncthreads();
+    }
+    for (int x = tid; x < nK; x += FIN_WG) d.g[7 * d.p0 + x] = ys[x];
     __syncthreads();
   }
-  // ---- backward solve L^T x = y, levels from the root
-  for (int l = d.nlev - 1; l >= 0; --l) {
-    for (int cc = d.lev_ptr[l] + wv; cc < d.lev_ptr[l + 1]; cc += PGO_WG / 64) {
-      const int c = d.lev_col[cc];
-      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-      for (int b = d.col_ptr[c] + lane; b < d.col_ptr[c + 1]; b += 64) {
-        const double* L = d.Lb + 49 * b;
-        const double* x = d.g + 7 * d.blk_row[b];
-        for (int r = 0; r < 7; ++r)
-          for (int u = 0; u < 7; ++u) acc[u] += L[7 * r + u] * x[r];
-      }
-      wave_totals_f64(acc);
-      if (lane == 0) {  // x_c = L_cc^{-T} (x_c - acc)
-        const double* Di = d.Di + 49 * c;
-        double* x = d.g + 7 * c;
-        double v[7];
-#pragma unroll
-        for (int r = 0; r < 7; ++r) v[r] = x[r] - acc[r];
-#pragma unroll
-        for (int r = 0; r < 7; ++r) {
-          double t = 0.0;
-#pragma unroll
-          for (int k = r; k < 7; ++k) t += Di[7 * k + r] * v[k];
-          x[r] = t;
-        }
-      }
-    }
-    __syncthreads();
-  }
+  // ---- backward solve L^T x = y over the sparse columns, levels from the root
+  for (int l = d.nflev - 1; l >= 0; --l) solve_level<true>(d, l, prod);
   // ---- LM: reduction the quadratic model predicts, dx^T (lambda D dx - g) / 2 (fixed order)
   if (lm) {
     double part2 = 0.0;
-    for (int x = tid; x < d.m * 7; x += PGO_WG) part2 += d.g[x] * (lambda * d.dsave[x] * d.g[x] + d.gsave[x]);
-    const double pr = wg_sum(part2, sh);
+    for (int x = tid; x < d.m * 7; x += FIN_WG) part2 += d.g[x] * (lambda * d.dsave[x] * d.g[x] + d.gsave[x]);
+    const double pr = wg_sum<FIN_WG>(part2, sh);
     if (tid == 0) d.pred[0] = 0.5 * pr;
   }
   // ---- update T <- Exp(dx) T for the free nodes
-  for (int c = tid; c < d.m; c += PGO_WG) {
+  for (int c = tid; c < d.m; c += FIN_WG) {
     const int nd = d.node[c];
     const Sim3d E = sim3_exp(d.g + 7 * c);
     store_sim3(T + nd, sim3_compose(E, ld_pose(T + nd)));
@@ -582,10 +734,10 @@ struct PgoWorkspace {
 namespace {
 
 struct Symbolic {
-  int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, cp0 = 0;
+  int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
       up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk,
-      chain, dt_tgt, dt_ptr, dup_a, dup_b;
+      chain, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk;
   std::vector<int8_t> gv_sign;
 };
 
@@ -719,24 +871,12 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   int K = 0;
   for (int c = m - 1; c >= 0 && (int)cs[c].size() == m - 1 - c; --c) ++K;
   if (K < 8) K = 0;
-  if (K > PGO_KMAX) K = PGO_KMAX;
-  // every clique pair's block sits where the device computes it (column c holds its rows
-  // in order, and the clique's columns are consecutive); otherwise the clique is left
-  // to the sparse schedule
-  if (K > 0) {
-    const int q0 = m - K, cp0 = S.col_ptr[q0];
-    for (int k = 0; k < K && K > 0; ++k)
-      for (int i = k + 1; i < K; ++i)
-        if (block_of(q0 + i, q0 + k) != cp0 + k * (K - 1) - k * (k - 1) / 2 + (i - k - 1)) {
-          K = 0;
-          break;
-        }
-  }
+  if (K > PGO_KMAX) K = PGO_KMAX;  // the last PGO_KMAX columns of a larger clique are one too
   const int p0 = m - K;
   S.K = K;
   S.p0 = p0;
-  S.cp0 = K > 0 ? S.col_ptr[p0] : 0;
-  // factor schedule of the sparse columns (levels without one are dropped)
+  S.nF = K > 0 ? (7 * K + FT - 1) / FT * FT : 0;
+  // schedule of the sparse columns (levels without one are dropped)
   S.flev_ptr.assign(1, 0);
   S.lt_ptr.assign(1, 0);
   S.lb_ptr.assign(1, 0);
@@ -747,9 +887,10 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
       if (c >= p0) continue;
       any = true;
       S.flev_col.push_back(c);
-      S.lt_tgt.push_back(c);
+      auto has_updates = [&](int t) { return S.up_ptr[t + 1] > S.up_ptr[t]; };  // others keep their assembled value
+      if (has_updates(c)) S.lt_tgt.push_back(c);
       for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) {
-        S.lt_tgt.push_back(m + b);
+        if (has_updates(m + b)) S.lt_tgt.push_back(m + b);
         S.lb_blk.push_back(b);
       }
     }
@@ -778,6 +919,15 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   std::vector<std::vector<int>> rows(m);
   for (int b = 0; b < S.nblk; ++b) rows[S.blk_row[b]].push_back(b);
   flatten(rows, S.row_ptr, S.row_blk);
+  // the sparse columns' row and column blocks in schedule order, for the solves
+  S.fs_ptr.assign(1, 0);
+  S.bs_ptr.assign(1, 0);
+  for (int c : S.flev_col) {
+    S.fs_blk.insert(S.fs_blk.end(), rows[c].begin(), rows[c].end());
+    S.fs_ptr.push_back((int32_t)S.fs_blk.size());
+    for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) S.bs_blk.push_back(b);
+    S.bs_ptr.push_back((int32_t)S.bs_blk.size());
+  }
   // chaining order (breadth-first from the gauge over edges in input order)
   std::vector<std::vector<int>> inc(n);
   for (int k = 0; k < E; ++k) {
@@ -840,9 +990,11 @@ hipError_t launch_iteration(const PgoDev& d, s3a_sim3* T, double lambda, int it,
   const int ga = (int)std::min<int64_t>((work + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pgo_assemble, dim3(ga), dim3(256), 0, st, d, lambda, lm);
   hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(PGO_WG), 0, st, d, it, 1);
-  if (d.K > 0 && d.n_dt > 0)
+  if (d.K > 0) {
     hipLaunchKernelGGL(k_pgo_clique_updates, dim3((d.n_dt + 3) / 4), dim3(256), 0, st, d);
-  hipLaunchKernelGGL(k_pgo_finish, dim3(1), dim3(PGO_WG), 0, st, d, T, lambda, lm);
+    hipLaunchKernelGGL(k_pgo_front, dim3(1), dim3(FRONT_WG), 0, st, d);
+  }
+  hipLaunchKernelGGL(k_pgo_finish, dim3(1), dim3(FIN_WG), 0, st, d, T, lambda, lm);
   return hipGetLastError();
 }
 
@@ -1006,13 +1158,14 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.ob_ptr.size()) + bytes_of<int32_t>(S.ob_edge.size());
     total += bytes_of<int32_t>(S.gv_ptr.size()) + bytes_of<int32_t>(S.gv_edge.size()) + bytes_of<int8_t>(S.gv_sign.size());
     total += bytes_of<int32_t>(S.up_ptr.size()) + bytes_of<int32_t>(S.up_a.size()) * 2;
-    total += bytes_of<int32_t>(S.lev_ptr.size()) + bytes_of<int32_t>(S.lev_col.size());
     total += bytes_of<int32_t>(S.flev_ptr.size()) + bytes_of<int32_t>(S.flev_col.size() + 1);
     total += bytes_of<int32_t>(S.dt_tgt.size() + 1) + bytes_of<int32_t>(S.dt_ptr.size());
     total += bytes_of<int32_t>(S.dup_a.size() + 1) * 2;
     total += bytes_of<int32_t>(S.lt_ptr.size()) + bytes_of<int32_t>(S.lt_tgt.size() + 1);
     total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
+    total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
+    total += bytes_of<int32_t>(S.bs_ptr.size()) + bytes_of<int32_t>(S.bs_blk.size() + 1);
     total += bytes_of<int32_t>(S.chain.size() + 4);
     total += bytes_of<double>(49 * (size_t)m) * 2 + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
@@ -1020,6 +1173,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<double>(7 * (size_t)m + 7) * 2 + bytes_of<double>(8);  // LM: gsave, dsave, pred
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<s3a_sim3>(n_nodes);
+    total += bytes_of<double>((size_t)S.nF * S.nF + 1) + bytes_of<double>((size_t)S.nF * FB + 1);  // front
     if (ws->buf) {
       (void)hipStreamSynchronize(st);
       (void)hipFree(ws->buf);
@@ -1031,8 +1185,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     ws->buf = buf;
     char* c = static_cast<char*>(buf);
     PgoDev& d = ws->dev;
-    d.n_nodes = n_nodes; d.n_edges = E; d.m = m; d.gauge = p.gauge; d.nblk = nb; d.nlev = S.nlev;
-    d.nflev = S.nflev; d.K = S.K; d.p0 = S.p0; d.cp0 = S.cp0; d.n_dt = (int32_t)S.dt_tgt.size();
+    d.n_nodes = n_nodes; d.n_edges = E; d.m = m; d.gauge = p.gauge; d.nblk = nb;
+    d.nflev = S.nflev; d.K = S.K; d.p0 = S.p0; d.nF = S.nF; d.n_dt = (int32_t)S.dt_tgt.size();
     std::vector<int32_t> ei(E), ej(E);
     for (int k = 0; k < E; ++k) { ei[k] = ij[2 * k]; ej[k] = ij[2 * k + 1]; }
     std::vector<std::pair<void*, std::pair<const void*, size_t>>> up;
@@ -1056,8 +1210,6 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_upp = carve<int32_t>(c, S.up_ptr.size()); put(p_upp, S.up_ptr); d.up_ptr = p_upp;
     int32_t* p_upa = carve<int32_t>(c, S.up_a.size()); put(p_upa, S.up_a); d.up_a = p_upa;
     int32_t* p_upb = carve<int32_t>(c, S.up_b.size()); put(p_upb, S.up_b); d.up_b = p_upb;
-    int32_t* p_lvp = carve<int32_t>(c, S.lev_ptr.size()); put(p_lvp, S.lev_ptr); d.lev_ptr = p_lvp;
-    int32_t* p_lvc = carve<int32_t>(c, S.lev_col.size()); put(p_lvc, S.lev_col); d.lev_col = p_lvc;
     int32_t* p_flp = carve<int32_t>(c, S.flev_ptr.size()); put(p_flp, S.flev_ptr); d.flev_ptr = p_flp;
     int32_t* p_flc = carve<int32_t>(c, S.flev_col.size() + 1); put(p_flc, S.flev_col); d.flev_col = p_flc;
     int32_t* p_dtt = carve<int32_t>(c, S.dt_tgt.size() + 1); put(p_dtt, S.dt_tgt); d.dt_tgt = p_dtt;
@@ -1070,6 +1222,10 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_lbb = carve<int32_t>(c, S.lb_blk.size() + 1); put(p_lbb, S.lb_blk); d.lb_blk = p_lbb;
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
     int32_t* p_rwb = carve<int32_t>(c, S.row_blk.size()); put(p_rwb, S.row_blk); d.row_blk = p_rwb;
+    int32_t* p_fsp = carve<int32_t>(c, S.fs_ptr.size()); put(p_fsp, S.fs_ptr); d.fs_ptr = p_fsp;
+    int32_t* p_fsb = carve<int32_t>(c, S.fs_blk.size() + 1); put(p_fsb, S.fs_blk); d.fs_blk = p_fsb;
+    int32_t* p_bsp = carve<int32_t>(c, S.bs_ptr.size()); put(p_bsp, S.bs_ptr); d.bs_ptr = p_bsp;
+    int32_t* p_bsb = carve<int32_t>(c, S.bs_blk.size() + 1); put(p_bsb, S.bs_blk); d.bs_blk = p_bsb;
     int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
     d.n_chain = (int32_t)(S.chain.size() / 4);
     d.Ld = carve<double>(c, 49 * (size_t)m);
@@ -1088,9 +1244,16 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     ws->v_alt = carve<double>(c, 7 * (size_t)E + 7);
     ws->r2_alt = carve<double>(c, E + 1);
     ws->T_bak = carve<s3a_sim3>(c, n_nodes);
+    d.F = carve<double>(c, (size_t)S.nF * S.nF + 1);
+    d.Finv = carve<double>(c, (size_t)S.nF * FB + 1);
     for (auto& u : up) {
       e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return fail(last_hip, e);
+    }
+    if (d.nF > 0) {  // identity padding of the front; the clique's part is rewritten every iteration
+      const size_t nn = (size_t)d.nF * d.nF;
+      hipLaunchKernelGGL(k_pgo_front_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, d);
+      if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
     }
     e = hipStreamSynchronize(st);  // the host vectors go out of scope
     if (e != hipSuccess) return fail(last_hip, e);
