@@ -58,6 +58,9 @@ struct PgoDev {
   // column blocks bs_blk[bs_ptr[j]..] (backward solve), consecutive over a level
   int32_t nflev;
   const int32_t* flev_ptr; const int32_t* flev_col;
+  // the level's update pairs, target by target in lt_tgt order: target at position i
+  // gets -= L_a L_b^T for (a, b) in fu_a/fu_b[fu_ptr[i]..fu_ptr[i+1])
+  const int32_t* fu_ptr; const int32_t* fu_a; const int32_t* fu_b;
   const int32_t* fs_ptr; const int32_t* fs_blk;
   const int32_t* bs_ptr; const int32_t* bs_blk;
   const int32_t* lt_ptr; const int32_t* lt_tgt;
@@ -195,6 +198,7 @@ constexpr int FB = 32;
 constexpr int FT = 64;
 constexpr int FRONT_MAX = 512;
 constexpr int FRONT_WG = 512;
+typedef double d4 __attribute__((ext_vector_type(4)));
 static_assert((7 * PGO_KMAX + FT - 1) / FT * FT <= FRONT_MAX, "front order");
 constexpr int FIN_WG = 512;  // solves: 256 registers per lane
 static_assert(FIN_WG % FB == 0 && (FIN_WG / FB) <= 64 && ((FIN_WG / FB) & (FIN_WG / FB - 1)) == 0, "row slots per front column");
@@ -350,9 +354,13 @@ __global__ __launch_bounds__(256) void k_pgo_assemble(PgoDev d, double lambda, i
 
 // chi^2 at the linearisation point, then (update) the sparse columns' factorisation
 // level by level, by one workgroup.
+// Update products of one factor level kept in LDS at a time.
+constexpr int UPD_CHUNK = 256;
+
 __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int update) {
   __shared__ double sh[PGO_WG / 64 + 1];
   __shared__ int s_fail;
+  __shared__ double prod[49 * UPD_CHUNK];
   const int tid = threadIdx.x;
   if (*d.status != 0) return;
   double part = 0.0;
@@ -362,20 +370,50 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int upd
   if (!update) return;
   if (tid == 0) s_fail = 0;
   __syncthreads();
-  // ---- factorisation: the sparse part level by level, then the dense clique
-  const int lane = tid & 63, wv = tid >> 6;
+  // ---- factorisation of the sparse columns, level by level
   for (int l = 0; l < d.nflev; ++l) {
     const int c0 = d.flev_ptr[l], c1 = d.flev_ptr[l + 1];
-    // (A) every update target of this level (diagonal and off-diagonal blocks of its columns)
+    // (A) the updates of this level's targets (diagonal and off-diagonal blocks of its
+    // columns), in chunks of UPD_CHUNK pairs: every product row L_a(r,:) L_b^T by one
+    // thread into LDS, then one thread per (target, row) subtracts its products' sum
+    // (list order, chunk after chunk)
     {
-      const int t0 = d.lt_ptr[l], nt = d.lt_ptr[l + 1] - t0;
-      for (int ti = wv; ti < nt; ti += PGO_WG / 64) {
-        const int target = d.lt_tgt[t0 + ti];
-        double* e = target_elem(d, target, lane);
-        update_target(d, e, e, d.up_ptr[target], d.up_ptr[target + 1], d.up_a, d.up_b, lane);
+      const int i0 = d.lt_ptr[l], i1 = d.lt_ptr[l + 1];
+      const int q0 = d.fu_ptr[i0], q1 = d.fu_ptr[i1];
+      for (int base = q0; base < q1; base += UPD_CHUNK) {
+        const int top = min(base + UPD_CHUNK, q1);
+        for (int it = tid; it < (top - base) * 7; it += PGO_WG) {
+          const int q = base + it / 7, r = it % 7;
+          const double* La = d.Lb + 49 * d.fu_a[q] + 7 * r;
+          const double* LB = d.Lb + 49 * d.fu_b[q];
+          double a[7];
+#pragma unroll
+          for (int u = 0; u < 7; ++u) a[u] = La[u];
+#pragma unroll
+          for (int c = 0; c < 7; ++c) {
+            double t = 0.0;
+#pragma unroll
+            for (int u = 0; u < 7; ++u) t += a[u] * LB[7 * c + u];
+            prod[49 * (q - base) + 7 * r + c] = t;
+          }
+        }
+        __syncthreads();
+        for (int it = tid; it < (i1 - i0) * 7; it += PGO_WG) {
+          const int i = i0 + it / 7, r = it % 7;
+          const int lo = max(d.fu_ptr[i], base), hi = min(d.fu_ptr[i + 1], top);
+          if (lo >= hi) continue;
+          const int t = d.lt_tgt[i];
+          double* T = (t < d.m ? d.Ld + 49 * t : d.Lb + 49 * (t - d.m)) + 7 * r;
+#pragma unroll
+          for (int c = 0; c < 7; ++c) {
+            double acc = 0.0;
+            for (int q = lo; q < hi; ++q) acc += prod[49 * (q - base) + 7 * r + c];
+            T[c] -= acc;
+          }
+        }
+        __syncthreads();
       }
     }
-    __syncthreads();
     // (B) Cholesky of each diagonal block of the level (and its inverse): one lane per block
     for (int cc = c0 + tid; cc < c1; cc += PGO_WG) {
       const int col = d.flev_col[cc];
@@ -432,7 +470,7 @@ __device__ inline double readlane_f64(double x, int l) {
 //      thread, written to F and to an LDS copy of the panel (column-major by row);
 //      one wavefront meanwhile inverts L_kk for the triangular solves;
 //  (3) the trailing lower triangle A -= P P^T in FT x FT tiles, one wavefront per
-//      tile, an 8 x 8 register block per lane, the panel read from LDS.
+//      tile, on the FP64 matrix cores (16 x 16 x 4 products, the panel read from LDS).
 __global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
   __shared__ double P[FB * FRONT_MAX];  // panel: P[k * FRONT_MAX + i], i = row - (k0 + FB)
   __shared__ double Ls[FB * FB];        // diagonal factor, row-major, zero above the diagonal
@@ -513,40 +551,52 @@ __global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
     __syncthreads();
     // (3)
     const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
-    const int lr = lane >> 3, lc = lane & 7;
+    const int l16 = lane & 15, l4 = lane >> 4;
     for (int ti = wv; ti < ntile; ti += FRONT_WG / 64) {
       int I = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
       I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
       I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
       const int J = ti - I * (I + 1) / 2;
-      const int r0 = FT * I + 8 * lr, c0 = FT * J + 8 * lc;  // relative to s0; nr is a multiple of 8
-      const bool in = r0 < nr && c0 < nr;
-      double* blk = F + (in ? (size_t)(s0 + c0) * n + s0 + r0 : 0);
-      double acc[8][8];
+      // the tile transposed: D[j][i] = A[i][j] for rows i in 64 I.., columns j in 64 J..
+      // (relative to s0); 16 x 16 blocks (cj, ri), lane holds D[jb + l4 + 4 v][ib + l16],
+      // i.e. four runs of 16 consecutive rows of F's columns
+      d4 acc[4][4];
+      bool live[4][4];
 #pragma unroll
-      for (int v = 0; v < 8; ++v)
+      for (int cj = 0; cj < 4; ++cj)
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc[u][v] = blk[(size_t)v * n + u];
-#pragma unroll 4
-      for (int k = 0; k < FB; ++k) {
-        double pa[8], pb[8];
+        for (int ri = 0; ri < 4; ++ri) {
+          const int ib = FT * I + 16 * ri, jb = FT * J + 16 * cj;
+          live[cj][ri] = ib < nr && jb < nr && (I != J || ri >= cj);
+          const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          pa[u] = P[k * FRONT_MAX + r0 + u];
-          pb[u] = P[k * FRONT_MAX + c0 + u];
+          for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
+        }
+#pragma unroll 2
+      for (int k = 0; k < FB; k += 4) {
+        double pa[4], pb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          pa[q] = -P[(k + l4) * FRONT_MAX + FT * J + 16 * q + l16];
+          pb[q] = P[(k + l4) * FRONT_MAX + FT * I + 16 * q + l16];
         }
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
+        for (int cj = 0; cj < 4; ++cj)
 #pragma unroll
-          for (int u = 0; u < 8; ++u) acc[u][v] -= pa[u] * pb[v];
+          for (int ri = 0; ri < 4; ++ri)
+            if (live[cj][ri]) acc[cj][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[cj], pb[ri], acc[cj][ri], 0, 0, 0);
       }
-      if (in) {
 #pragma unroll
-        for (int v = 0; v < 8; ++v)
+      for (int cj = 0; cj < 4; ++cj)
 #pragma unroll
-          for (int u = 0; u < 8; ++u)
-            if (I != J || r0 + u >= c0 + v) blk[(size_t)v * n + u] = acc[u][v];
-      }
+        for (int ri = 0; ri < 4; ++ri) {
+          if (!live[cj][ri]) continue;
+          const int ib = FT * I + 16 * ri, jb = FT * J + 16 * cj;
+          double* dst = F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16;
+#pragma unroll
+          for (int v = 0; v < 4; ++v)
+            if (I != J || ib + l16 >= jb + l4 + 4 * v) dst[(size_t)(4 * v) * n] = acc[cj][ri][v];
+        }
     }
     __syncthreads();
   }
@@ -737,7 +787,7 @@ struct Symbolic {
   int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
       up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk,
-      chain, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk;
+      chain, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b;
   std::vector<int8_t> gv_sign;
 };
 
@@ -919,6 +969,15 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   std::vector<std::vector<int>> rows(m);
   for (int b = 0; b < S.nblk; ++b) rows[S.blk_row[b]].push_back(b);
   flatten(rows, S.row_ptr, S.row_blk);
+  // the update pairs of the sparse columns' targets, in schedule order
+  S.fu_ptr.assign(1, 0);
+  for (int t : S.lt_tgt) {
+    for (int q = S.up_ptr[t]; q < S.up_ptr[t + 1]; ++q) {
+      S.fu_a.push_back(S.up_a[q]);
+      S.fu_b.push_back(S.up_b[q]);
+    }
+    S.fu_ptr.push_back((int32_t)S.fu_a.size());
+  }
   // the sparse columns' row and column blocks in schedule order, for the solves
   S.fs_ptr.assign(1, 0);
   S.bs_ptr.assign(1, 0);
@@ -1165,6 +1224,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
+    total += bytes_of<int32_t>(S.fu_ptr.size()) + bytes_of<int32_t>(S.fu_a.size() + 1) * 2;
     total += bytes_of<int32_t>(S.bs_ptr.size()) + bytes_of<int32_t>(S.bs_blk.size() + 1);
     total += bytes_of<int32_t>(S.chain.size() + 4);
     total += bytes_of<double>(49 * (size_t)m) * 2 + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
@@ -1223,6 +1283,9 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
     int32_t* p_rwb = carve<int32_t>(c, S.row_blk.size()); put(p_rwb, S.row_blk); d.row_blk = p_rwb;
     int32_t* p_fsp = carve<int32_t>(c, S.fs_ptr.size()); put(p_fsp, S.fs_ptr); d.fs_ptr = p_fsp;
+    int32_t* p_fup = carve<int32_t>(c, S.fu_ptr.size()); put(p_fup, S.fu_ptr); d.fu_ptr = p_fup;
+    int32_t* p_fua = carve<int32_t>(c, S.fu_a.size() + 1); put(p_fua, S.fu_a); d.fu_a = p_fua;
+    int32_t* p_fub = carve<int32_t>(c, S.fu_b.size() + 1); put(p_fub, S.fu_b); d.fu_b = p_fub;
     int32_t* p_fsb = carve<int32_t>(c, S.fs_blk.size() + 1); put(p_fsb, S.fs_blk); d.fs_blk = p_fsb;
     int32_t* p_bsp = carve<int32_t>(c, S.bs_ptr.size()); put(p_bsp, S.bs_ptr); d.bs_ptr = p_bsp;
     int32_t* p_bsb = carve<int32_t>(c, S.bs_blk.size() + 1); put(p_bsb, S.bs_blk); d.bs_blk = p_bsb;
