@@ -462,104 +462,134 @@ __device__ inline double readlane_f64(double x, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
+// LDS of the front's diagonal-block step (file scope, so that its addresses are
+// constants for the non-inlined function that uses them).
+__shared__ double front_Vs[FB * FB];         // inverse of the panel's diagonal factor, row-major
+__shared__ double front_LsT[FB * (FB + 1)];  // the diagonal factor by column
+__shared__ double front_cb[2 * (FB + 1)];    // columns being broadcast
+
+// (1) of the front factorisation for the diagonal block at (kd, kd), by one
+// wavefront. The factor: lane = row, right-looking; the pivot is read from its
+// lane, and each updated column is written to LDS (cb, two buffers used in turn)
+// one step before it is needed, so no step waits for LDS. The factor goes back
+// to F and, by column, to front_LsT. Its inverse: lane = column, right-looking
+// forward substitution against e_lane, to front_Vs and Vg, row-major. LDS traffic of one
+// wavefront is processed in order, so its reads see its earlier writes. False (in
+// every lane) if a pivot is not positive.
+__device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, double* Vg) {
+  double* cb = front_cb;
+  double* LsT = front_LsT;
+  double* Vs = front_Vs;
+  const int r = lane < FB ? lane : FB - 1, e = lane < FB ? lane : FB;
+  double a[FB];  // row r; entries above the diagonal carry values that are never read
+#pragma unroll
+  for (int c = 0; c < FB; ++c) a[c] = F[(size_t)(kd + c) * n + kd + (c <= r ? r : c)];
+  bool ok = true;
+  double rv = 1.0;
+  cb[e] = a[0];
+#pragma unroll
+  for (int k = 0; k < FB; ++k) {
+    double* cur = cb + (k & 1) * (FB + 1);
+    double* nxt = cb + ((k + 1) & 1) * (FB + 1);
+    const double dkk = readlane_f64(a[k], k);
+    ok = ok && dkk > 0.0;
+    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0), rk = 1.0 / lkk;
+    a[k] = lane == k ? lkk : a[k] * rk;
+    rv = lane == k ? rk : rv;
+    LsT[k * (FB + 1) + e] = a[k];
+    const double m = a[k] * rk;  // L_rk / L_kk, and L_jk = cur[j] / L_kk
+    if (k + 1 < FB) {
+      a[k + 1] -= m * cur[k + 1];
+      nxt[e] = a[k + 1];
+    }
+#pragma unroll
+    for (int j = k + 2; j < FB; ++j) a[j] -= m * cur[j];
+  }
+  if (lane < FB) {
+#pragma unroll
+    for (int c = 0; c < FB; ++c)
+      if (c <= lane) F[(size_t)(kd + c) * n + kd + lane] = a[c];
+  }
+  cb[e] = rv;
+  double t[FB];
+#pragma unroll
+  for (int i = 0; i < FB; ++i) t[i] = i == lane ? 1.0 : 0.0;
+#pragma unroll
+  for (int k = 0; k < FB; ++k) {
+    const double v = t[k] * cb[k];
+    t[k] = v;
+#pragma unroll
+    for (int i = k + 1; i < FB; ++i) t[i] -= LsT[k * (FB + 1) + i] * v;
+  }
+  if (lane < FB) {
+#pragma unroll
+    for (int i = 0; i < FB; ++i) {
+      Vs[i * FB + lane] = t[i];
+      Vg[i * FB + lane] = t[i];
+    }
+  }
+  return ok;
+}
+
 // Right-looking blocked Cholesky of the front F (order nF, column-major, lower
 // triangle) in place, by one workgroup, panel by panel of FB columns:
-//  (1) the FB x FB diagonal block by one wavefront, lane = row, the pivot column
-//      read across lanes; its factor also goes to LDS, with the reciprocal pivots;
-//  (2) the rows below: L_i = A_i L_kk^{-T} by forward substitution, one row per
-//      thread, written to F and to an LDS copy of the panel (column-major by row);
-//      one wavefront meanwhile inverts L_kk for the triangular solves;
+//  (1) the FB x FB diagonal block and its inverse by one wavefront (front_diag);
+//      the inverse goes to LDS (for (2)) and to Finv (for the solves);
+//  (2) the rows below: L_i = A_i L_kk^{-T} = A_i (L_kk^{-1})^T on the FP64 matrix
+//      cores, one wavefront per 16 rows, written to F and to an LDS copy of the
+//      panel (P, by column);
 //  (3) the trailing lower triangle A -= P P^T in FT x FT tiles, one wavefront per
-//      tile, on the FP64 matrix cores (16 x 16 x 4 products, the panel read from LDS).
+//      tile, on the matrix cores (16 x 16 x 4 products). Wavefront 0 takes the
+//      leading corner of the first tile, the next panel's diagonal block, and then
+//      factors that block (1) while the others finish the trailing update.
+// Matrix-core tiles are computed transposed (D[j][i] for the element (i, j)) so
+// that every lane group reads and writes 16 consecutive rows of a column of F.
 __global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
-  __shared__ double P[FB * FRONT_MAX];  // panel: P[k * FRONT_MAX + i], i = row - (k0 + FB)
-  __shared__ double Ls[FB * FB];        // diagonal factor, row-major, zero above the diagonal
-  __shared__ double rinv[FB];
+  __shared__ double P[FB * FRONT_MAX];  // panel: P[k * FRONT_MAX + i] = L(k0 + FB + i, k0 + k)
   __shared__ int s_fail;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int l16 = lane & 15, l4 = lane >> 4;
   if (*d.status != 0) return;
   if (tid == 0) s_fail = 0;
+  __syncthreads();
   const int n = d.nF;
   double* F = d.F;
-  for (int k0 = 0; k0 < n; k0 += FB) {
-    // (1)
-    if (wv == 0) {
-      const int r = lane < FB ? lane : FB - 1;
-      double a[FB];
-#pragma unroll
-      for (int c = 0; c < FB; ++c) a[c] = F[(size_t)(k0 + c) * n + k0 + (c <= r ? r : c)];
-#pragma unroll
-      for (int c = 0; c < FB; ++c) a[c] = c <= r ? a[c] : 0.0;
-      bool ok = true;
-      double rv = 1.0;
-#pragma unroll
-      for (int k = 0; k < FB; ++k) {
-        const double dkk = readlane_f64(a[k], k);
-        ok = ok && dkk > 0.0;
-        const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0), rk = 1.0 / lkk;
-        a[k] = lane == k ? lkk : a[k] * rk;
-        rv = lane == k ? rk : rv;
-        // rows above j pick up values above the diagonal here; they are never read
-#pragma unroll
-        for (int j = k + 1; j < FB; ++j) a[j] -= a[k] * readlane_f64(a[k], j);
-      }
-      if (lane < FB) {
-#pragma unroll
-        for (int c = 0; c < FB; ++c) {
-          if (c <= lane) F[(size_t)(k0 + c) * n + k0 + lane] = a[c];
-          Ls[lane * FB + c] = c <= lane ? a[c] : 0.0;
-        }
-        rinv[lane] = rv;
-      }
-      if (!ok && lane == 0) s_fail = 1;
-    }
-    __syncthreads();
+  // pass k0 = -FB only factors the first diagonal block
+  for (int k0 = -FB; k0 < n; k0 += FB) {
     if (s_fail) break;
+    const int s0 = k0 + FB, nr = n - s0;  // nr: a multiple of FB
     // (2)
-    const int s0 = k0 + FB, nr = n - s0;
-    if (tid < nr) {  // nr < FRONT_WG: one row per thread
-      double x[FB];
+    for (int ib = 16 * wv; k0 >= 0 && ib < nr; ib += 16 * (FRONT_WG / 64)) {
+      d4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
+      double bv[FB / 4];
 #pragma unroll
-      for (int c = 0; c < FB; ++c) x[c] = F[(size_t)(k0 + c) * n + s0 + tid];
+      for (int q = 0; q < FB / 4; ++q) bv[q] = F[(size_t)(k0 + 4 * q + l4) * n + s0 + ib + l16];
 #pragma unroll
-      for (int c = 0; c < FB; ++c) {
-        double v = x[c];
-#pragma unroll
-        for (int k = 0; k < c; ++k) v -= x[k] * Ls[c * FB + k];
-        x[c] = v * rinv[c];
+      for (int q = 0; q < FB / 4; ++q) {
+        // columns 0..15 of the inverse vanish beyond column 15
+        if (q < FB / 8) x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(front_Vs[l16 * FB + 4 * q + l4], bv[q], x0, 0, 0, 0);
+        x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(front_Vs[(16 + l16) * FB + 4 * q + l4], bv[q], x1, 0, 0, 0);
       }
 #pragma unroll
-      for (int c = 0; c < FB; ++c) {
-        F[(size_t)(k0 + c) * n + s0 + tid] = x[c];
-        P[c * FRONT_MAX + tid] = x[c];
+      for (int v = 0; v < 4; ++v) {
+        const int c = l4 + 4 * v, i = ib + l16;
+        F[(size_t)(k0 + c) * n + s0 + i] = x0[v];
+        F[(size_t)(k0 + 16 + c) * n + s0 + i] = x1[v];
+        P[c * FRONT_MAX + i] = x0[v];
+        P[(16 + c) * FRONT_MAX + i] = x1[v];
       }
-    }
-    if (wv == FRONT_WG / 64 - 1 && lane < FB) {
-      // column `lane` of L_kk^{-1}: forward substitution against e_lane
-      double v[FB];
-#pragma unroll
-      for (int r = 0; r < FB; ++r) {
-        double t = r == lane ? 1.0 : 0.0;
-#pragma unroll
-        for (int k = 0; k < r; ++k) t -= Ls[r * FB + k] * v[k];
-        v[r] = t * rinv[r];
-      }
-      double* Vi = d.Finv + (size_t)(k0 / FB) * FB * FB;
-#pragma unroll
-      for (int r = 0; r < FB; ++r) Vi[r * FB + lane] = v[r];
     }
     __syncthreads();
     // (3)
-    const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
-    const int l16 = lane & 15, l4 = lane >> 4;
-    for (int ti = wv; ti < ntile; ti += FRONT_WG / 64) {
+    const int T = k0 >= 0 ? (nr + FT - 1) / FT : 0, ntile = T * (T + 1) / 2;
+    // part 0: all of the tile; 1: the blocks of its leading 32 x 32 corner; 2: the rest
+    auto tile = [&](int ti, int part) {
       int I = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
       I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
       I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
       const int J = ti - I * (I + 1) / 2;
-      // the tile transposed: D[j][i] = A[i][j] for rows i in 64 I.., columns j in 64 J..
-      // (relative to s0); 16 x 16 blocks (cj, ri), lane holds D[jb + l4 + 4 v][ib + l16],
-      // i.e. four runs of 16 consecutive rows of F's columns
+      // rows i in 64 I.., columns j in 64 J.. (relative to s0); 16 x 16 blocks (cj, ri),
+      // the lane holds D[jb + l4 + 4 v][ib + l16]
       d4 acc[4][4];
       bool live[4][4];
 #pragma unroll
@@ -567,7 +597,8 @@ __global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
 #pragma unroll
         for (int ri = 0; ri < 4; ++ri) {
           const int ib = FT * I + 16 * ri, jb = FT * J + 16 * cj;
-          live[cj][ri] = ib < nr && jb < nr && (I != J || ri >= cj);
+          const bool corner = cj < 2 && ri < 2;
+          live[cj][ri] = ib < nr && jb < nr && (I != J || ri >= cj) && (part == 0 || (part == 1) == corner);
           const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
 #pragma unroll
           for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
@@ -597,6 +628,20 @@ __global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
           for (int v = 0; v < 4; ++v)
             if (I != J || ib + l16 >= jb + l4 + 4 * v) dst[(size_t)(4 * v) * n] = acc[cj][ri][v];
         }
+    };
+    if (wv == 0) {
+      if (k0 < 0 || ntile > 0) {
+        if (k0 >= 0) {
+          tile(0, 1);
+          __threadfence_block();  // the corner's stores before the next diagonal block is read
+        }
+        if (!front_diag(F, n, s0, lane, d.Finv + (size_t)(s0 / FB) * FB * FB) &&
+            lane == 0)
+          s_fail = 1;
+      }
+    } else {
+      // item 0: the rest of tile 0; item t > 0: tile t
+      for (int it = wv - 1; it < ntile; it += FRONT_WG / 64 - 1) tile(it, it == 0 ? 2 : 0);
     }
     __syncthreads();
   }
