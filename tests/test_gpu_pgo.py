@@ -185,3 +185,21 @@ def test_lm_full_loop_closure_graph(h):
     assert np.all(np.diff(chi) < 0)
     H, g, _ = pgo.normal_equations(T, E, meas)
     assert np.abs(g[7:]).max() < 1e-8 * max(1.0, np.abs(H).max())
+
+
+@pytest.mark.parametrize("n", [10, 21, 80])
+def test_complete_graphs(h, n):
+    """Complete graphs: every free node belongs to one dense clique, which is
+    factored as a dense front. With 9 and 20 free nodes the front is the whole
+    system and there are no sparse columns. With 79 free nodes the front takes
+    the last 72, and the other 7 are sparse columns, whose update lists fill
+    more than one chunk of products."""
+    rng = np.random.default_rng(100 + n)
+    Tgt = np.array([np.eye(4)] + [rand_pose(rng) for _ in range(n - 1)])
+    E = np.array([(i, j) for i in range(n) for j in range(i + 1, n)])
+    meas = np.array([sim3.exp(0.02 * rng.normal(size=7)) @ sim3.inv(Tgt[i]) @ Tgt[j] for i, j in E])
+    T, rep = run_gpu(h, E, meas, n, iters=4)
+    ref = pgo.pgo_solve(n, E, meas, iters=4)
+    assert rep.status == 0 and ref["status"] == 0
+    assert pose_err(T, ref["T"]) <= TOL
+    assert np.allclose(np.array(rep.chi2[:4]), ref["chi2"], rtol=1e-8)
