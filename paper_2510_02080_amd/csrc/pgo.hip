@@ -84,6 +84,7 @@ struct PgoDev {
   double* Lb;     // [nblk][49]
   double* g;      // [m][7]  gradient, then solution
   double* M;      // [E][49] per-edge psi A^T Omega A
+  double* Aw;     // [E][56] per-edge Jacobian A and Om e (scratch of the linearisation)
   double* v;      // [E][7]  per-edge psi A^T Omega e
   double* r2;     // [E]     e^T Omega e
   double* chi2;   // [iters + 1]
@@ -109,12 +110,26 @@ __global__ void k_pgo_chain(PgoDev d, const s3a_sim3* __restrict__ Tm, s3a_sim3*
   }
 }
 
-// One lane per edge: residual, Jacobian A, Huber weight, M = psi A^T Om A, v = psi A^T Om e.
-__global__ __launch_bounds__(128) void k_pgo_linearize(PgoDev d, const s3a_sim3* __restrict__ Tm,
-                                                      const double* __restrict__ omega, const s3a_sim3* __restrict__ T,
-                                                      double huber, int r2_only) {
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= d.n_edges) return;
+// Orders the LDS writes of a wavefront's lanes before the reads that follow, for
+// lanes that exchange values through LDS without a workgroup barrier.
+__device__ inline void wave_sync() { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); }
+
+// Edges per wavefront in the linearisation (seven lanes each).
+constexpr int LIN_EDGES = 9;
+
+// Seven lanes per edge, lane i = row i: residual e = Log(T_ij^{-1} T_i^{-1} T_j),
+// e^T Om e, and row i of the Jacobian A = J_r(e)^{-1} Ad(T_j^{-1}) into Aw (with
+// Om e after it). Row i of J_r = sum_n (-ad e)^n / (n+1)! is formed by the lane
+// alone; the inverse is Gauss-Jordan with partial pivoting on rows shared in LDS
+// within the wavefront. M = psi A^T Om A and
+// v = psi A^T Om e follow in k_pgo_edge_M.
+__global__ __launch_bounds__(64) void k_pgo_linearize(PgoDev d, const s3a_sim3* __restrict__ Tm,
+                                                     const double* __restrict__ omega, const s3a_sim3* __restrict__ T,
+                                                     double huber, int r2_only) {
+  __shared__ double aug[LIN_EDGES][7][14];
+  const int lane = threadIdx.x, g = lane / 7, i = lane % 7;
+  const int k = blockIdx.x * LIN_EDGES + g;
+  if (g >= LIN_EDGES || k >= d.n_edges) return;
   const Sim3d Ti = ld_pose(T + d.ei[k]);
   const Sim3d Tj = ld_pose(T + d.ej[k]);
   const Sim3d Tij = ld_pose(Tm + k);
@@ -131,44 +146,111 @@ __global__ __launch_bounds__(128) void k_pgo_linearize(PgoDev d, const s3a_sim3*
   }
   double q = 0.0;
   for (int a = 0; a < 7; ++a) q += e[a] * Oe[a];
-  d.r2[k] = q;
+  if (i == 0) d.r2[k] = q;
   if (r2_only) return;
+  double* Ag = d.Aw + 56 * k;
+  if (i == 0)
+    for (int a = 0; a < 7; ++a) Ag[49 + a] = Oe[a];
+  double row[14];
+  {
+    double A[49];
+    sim3_ad(e, A);
+    double P[7];
+    for (int j = 0; j < 7; ++j) {
+      P[j] = j == i ? 1.0 : 0.0;
+      row[j] = P[j];
+    }
+    for (int n = 1; n < 80; ++n) {
+      double Q[7], mx = 0.0;
+      for (int j = 0; j < 7; ++j) {
+        double v = 0.0;
+        for (int c = 0; c < 7; ++c) v -= P[c] * A[7 * c + j];
+        Q[j] = v / (double)(n + 1);
+      }
+      for (int j = 0; j < 7; ++j) {
+        P[j] = Q[j];
+        row[j] += Q[j];
+        const double x = fabs(Q[j]);
+        mx = x > mx ? x : mx;
+      }
+      if (mx < 1e-18) break;
+    }
+  }
+  for (int j = 0; j < 7; ++j) row[7 + j] = j == i ? 1.0 : 0.0;
+  double(*M)[14] = aug[g];
+  for (int j = 0; j < 14; ++j) M[i][j] = row[j];
+  wave_sync();
+  bool ok = true;
+  for (int c = 0; c < 7; ++c) {
+    int p = c;
+    for (int r = c + 1; r < 7; ++r)
+      if (fabs(M[r][c]) > fabs(M[p][c])) p = r;
+    ok = ok && M[p][c] != 0.0;
+    if (p != c && (i == c || i == p)) {  // exchange rows c and p
+      const int o = i == c ? p : c;
+      for (int j = 0; j < 14; ++j) row[j] = M[o][j];
+      wave_sync();
+      for (int j = 0; j < 14; ++j) M[i][j] = row[j];
+    }
+    wave_sync();
+    const double dv = ok ? 1.0 / M[c][c] : 0.0;
+    const double f = i == c ? 0.0 : M[i][c];
+    for (int j = 0; j < 14; ++j) row[j] = i == c ? M[c][j] * dv : M[i][j] - f * (M[c][j] * dv);
+    wave_sync();
+    for (int j = 0; j < 14; ++j) M[i][j] = row[j];
+    wave_sync();
+  }
+  double Ad[49];
+  sim3_Ad(sim3_inverse(Tj), Ad);
+  for (int b = 0; b < 7; ++b) {
+    double s = 0.0;
+    for (int c = 0; c < 7; ++c) s += row[7 + c] * Ad[7 * c + b];
+    Ag[7 * i + b] = ok ? s : __builtin_nan("");
+  }
+}
+
+// M = psi A^T (Om A) and v = psi A^T (Om e) per edge, one thread per element,
+// over the whole chip.
+__global__ __launch_bounds__(256) void k_pgo_edge_M(PgoDev d, const double* __restrict__ omega, double huber) {
+  const int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (x >= (int64_t)d.n_edges * 56) return;
+  const int k = (int)(x / 56), t = (int)(x % 56);
+  const double q = d.r2[k];
   const double r = sqrt(q > 0.0 ? q : 0.0);
   const double psi = r <= huber ? 1.0 : huber / r;
-  double Jr[49], Jri[49], Ad[49];
-  sim3_jacobian(e, -1.0, Jr);
-  if (!inv7(Jr, Jri)) {
-    for (int a = 0; a < 49; ++a) d.M[49 * k + a] = __builtin_nan("");
-    for (int a = 0; a < 7; ++a) d.v[7 * k + a] = __builtin_nan("");
+  const double* A = d.Aw + 56 * k;
+  if (t >= 49) {
+    const int b = t - 49;
+    double s = 0.0;
+    for (int a = 0; a < 7; ++a) s += A[7 * a + b] * A[49 + a];
+    d.v[7 * k + b] = psi * s;
     return;
   }
-  sim3_Ad(sim3_inverse(Tj), Ad);
-  double A[49];
-  for (int a = 0; a < 7; ++a)
-    for (int b = 0; b < 7; ++b) {
-      double s = 0.0;
-      for (int c = 0; c < 7; ++c) s += Jri[7 * a + c] * Ad[7 * c + b];
-      A[7 * a + b] = s;
+  const int a = t / 7, b = t % 7;
+  const double* Om = omega ? omega + 49 * k : nullptr;
+  double s = 0.0;
+  for (int c = 0; c < 7; ++c) {
+    double oab = A[7 * c + b];  // (Om A)[c][b]
+    if (Om) {
+      oab = 0.0;
+      for (int u = 0; u < 7; ++u) oab += Om[7 * c + u] * A[7 * u + b];
     }
-  // Om A (7x7), then M = psi A^T (Om A), v = psi A^T Om e
-  double OA[49];
-  for (int a = 0; a < 7; ++a)
-    for (int b = 0; b < 7; ++b) {
-      double s = 0.0;
-      if (Om) for (int c = 0; c < 7; ++c) s += Om[7 * a + c] * A[7 * c + b];
-      else s = A[7 * a + b];
-      OA[7 * a + b] = s;
-    }
-  for (int a = 0; a < 7; ++a) {
-    for (int b = 0; b < 7; ++b) {
-      double s = 0.0;
-      for (int c = 0; c < 7; ++c) s += A[7 * c + a] * OA[7 * c + b];
-      d.M[49 * k + 7 * a + b] = psi * s;
-    }
-    double s = 0.0;
-    for (int c = 0; c < 7; ++c) s += A[7 * c + a] * Oe[c];
-    d.v[7 * k + a] = psi * s;
+    s += A[7 * c + a] * oab;
   }
+  d.M[49 * k + 7 * a + b] = psi * s;
+}
+
+// Per-edge linearisation at T into d (r2 only, or r2, v and M).
+hipError_t launch_linearize(const PgoDev& d, const s3a_sim3* Tm, const double* omega, const s3a_sim3* T, double huber,
+                            int r2_only, hipStream_t st) {
+  if (d.n_edges == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pgo_linearize, dim3((d.n_edges + LIN_EDGES - 1) / LIN_EDGES), dim3(64), 0, st, d, Tm, omega, T,
+                     huber, r2_only);
+  if (!r2_only) {
+    const int64_t nx = (int64_t)d.n_edges * 56;
+    hipLaunchKernelGGL(k_pgo_edge_M, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, d, omega, huber);
+  }
+  return hipGetLastError();
 }
 
 constexpr int PGO_WG = 1024;
@@ -471,11 +553,11 @@ __shared__ double front_cb[2 * (FB + 1)];    // columns being broadcast
 // (1) of the front factorisation for the diagonal block at (kd, kd), by one
 // wavefront. The factor: lane = row, right-looking; the pivot is read from its
 // lane, and each updated column is written to LDS (cb, two buffers used in turn)
-// one step before it is needed, so no step waits for LDS. The factor goes back
-// to F and, by column, to front_LsT. Its inverse: lane = column, right-looking
-// forward substitution against e_lane, to front_Vs and Vg, row-major. LDS traffic of one
-// wavefront is processed in order, so its reads see its earlier writes. False (in
-// every lane) if a pivot is not positive.
+// one step before it is needed. The factor goes back to F and, by column, to
+// front_LsT. Its inverse: lane = column, right-looking forward substitution
+// against e_lane, to front_Vs and Vg, row-major. Lanes exchange values through
+// LDS with a wavefront fence between writes and reads. False (in every lane) if a
+// pivot is not positive.
 __device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, double* Vg) {
   double* cb = front_cb;
   double* LsT = front_LsT;
@@ -487,6 +569,7 @@ __device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, doub
   bool ok = true;
   double rv = 1.0;
   cb[e] = a[0];
+  wave_sync();
 #pragma unroll
   for (int k = 0; k < FB; ++k) {
     double* cur = cb + (k & 1) * (FB + 1);
@@ -504,13 +587,16 @@ __device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, doub
     }
 #pragma unroll
     for (int j = k + 2; j < FB; ++j) a[j] -= m * cur[j];
+    wave_sync();
   }
   if (lane < FB) {
 #pragma unroll
     for (int c = 0; c < FB; ++c)
       if (c <= lane) F[(size_t)(kd + c) * n + kd + lane] = a[c];
   }
+  wave_sync();
   cb[e] = rv;
+  wave_sync();
   double t[FB];
 #pragma unroll
   for (int i = 0; i < FB; ++i) t[i] = i == lane ? 1.0 : 0.0;
@@ -1121,15 +1207,13 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
   trial.M = ws->M_alt;
   trial.v = ws->v_alt;
   trial.r2 = ws->r2_alt;
-  const int lg = (n_edges + 127) / 128;
   const int max_rej = p.max_rejects > 0 ? p.max_rejects : 10;
   double lam = p.lambda > 0.0 ? p.lambda : 1e-4, nu = 2.0;
   std::vector<double> r2(n_edges), r2t(n_edges), chi;
   hipError_t e = hipSuccess;
   auto linearize = [&](const PgoDev& dd, std::vector<double>& out) -> hipError_t {
     if (n_edges == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_pgo_linearize, dim3(lg), dim3(128), 0, st, dd, T_meas, omega, T, p.huber_delta, 0);
-    hipError_t ee = hipGetLastError();
+    hipError_t ee = launch_linearize(dd, T_meas, omega, T, p.huber_delta, 0, st);
     if (ee == hipSuccess) ee = hipMemcpyAsync(out.data(), dd.r2, sizeof(double) * n_edges, hipMemcpyDeviceToHost, st);
     if (ee == hipSuccess) ee = hipStreamSynchronize(st);
     return ee;
@@ -1278,6 +1362,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<double>(7 * (size_t)m + 7) * 2 + bytes_of<double>(8);  // LM: gsave, dsave, pred
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<s3a_sim3>(n_nodes);
+    total += bytes_of<double>(56 * (size_t)E + 56);  // Aw
     total += bytes_of<double>((size_t)S.nF * S.nF + 1) + bytes_of<double>((size_t)S.nF * FB + 1);  // front
     if (ws->buf) {
       (void)hipStreamSynchronize(st);
@@ -1341,6 +1426,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     d.Lb = carve<double>(c, 49 * (size_t)nb + 49);
     d.g = carve<double>(c, 7 * (size_t)m + 7);
     d.M = carve<double>(c, 49 * (size_t)E + 49);
+    d.Aw = carve<double>(c, 56 * (size_t)E + 56);
     d.v = carve<double>(c, 7 * (size_t)E + 7);
     d.r2 = carve<double>(c, E + 1);
     d.chi2 = carve<double>(c, iters_cap);
@@ -1379,13 +1465,11 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     hipLaunchKernelGGL(k_pgo_chain, dim3(1), dim3(64), 0, st, d, T_meas, T);
     if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
   }
-  const int lg = (n_edges + 127) / 128;
   if (p.flags & S3A_PGO_LM) return pgo_solve_lm(ws, last_hip, n_nodes, n_edges, T_meas, omega, T, p, report, st);
   for (int it = 0; it <= p.iters; ++it) {
     const int update = it < p.iters;
     if (n_edges > 0) {
-      hipLaunchKernelGGL(k_pgo_linearize, dim3(lg), dim3(128), 0, st, d, T_meas, omega, T, p.huber_delta, !update);
-      if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
+      if ((e = launch_linearize(d, T_meas, omega, T, p.huber_delta, !update, st)) != hipSuccess) return fail(last_hip, e);
     }
     if (update && d.m == 0) continue;
     if ((e = launch_iteration(d, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
