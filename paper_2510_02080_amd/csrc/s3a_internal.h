@@ -23,9 +23,11 @@ constexpr int NSTAT = 19;
 //   17 sum w rho, 18 inlier count.
 enum PassMode { MODE_MOMENTS = 0, MODE_GN = 1, MODE_COST = 2, MODE_ADJOINT = 3 };
 
-// Tile boundaries are multiples of 8 elements so that 16-byte vector loads of
-// FP32 (4 elements) and BF16 (8 elements) planes are aligned.
-constexpr int64_t TILE_ALIGN = 8;
+// A pair's first tile starts at a multiple of 64 elements (its head is masked),
+// and tiles hold a multiple of 64 elements, so every tile boundary inside a pair
+// falls on a 128-byte line of each plane (FP32: 256 B, BF16: 128 B) and no line is
+// fetched by two tiles of the same pair; 16-byte vector loads stay aligned.
+constexpr int64_t TILE_ALIGN = 64;
 
 // Internal source types of the point passes: stored xyz (the public S3A_F32,
 // S3A_BF16) or depth maps unprojected on the fly (Sec. III-C.1, submaps from
