@@ -619,6 +619,84 @@ __device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const Tile
   block_store_f32<WG>(a, red, out);
 }
 
+// Moments of a depth-input tile whose pixels all lie in one frame. Each side is
+// formed in its camera's frame, x' = d (R ray) (coordinates of the size of the
+// scene, so FP32 products keep their precision), the products of the VEC pixels of
+// one vector are summed in FP32 and added to FP64 lane sums (the weight sum itself
+// in FP64 per pixel), and the lane sums are moved to the submap frame
+// (x = x' + t) once, in FP64, at the end.
+template <int DT, int WG, int ITEMS>
+__device__ inline void tile_moments_depth_frame(const Shape& sh, const SrcCtx<DT>& src, const TileDesc& td,
+                                                double (&a)[NSTAT], int& nvalid, int& nbad) {
+  using L = DepthPlanes<DT>;
+  constexpr int VEC = L::VEC;
+  const DepthCam& cp = src.cp;
+  const DepthCam& cq = src.cq;
+  const float tau = sh.tau;
+  const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+#pragma unroll 1
+  for (int it = 0; it < ITEMS; ++it) {
+    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+    if (rel0 >= end_rel) break;
+    float d[3][VEC];
+    L::load_raw(src, td.begin + rel0, sh.n_points, d);
+    int f, row, col;
+    L::position(src, td.begin + rel0, f, row, col);
+    float s[17];
+#pragma unroll
+    for (int j = 0; j < 17; ++j) s[j] = 0.0f;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
+      const float fc = (float)col, fr = (float)row;
+      const float rxp = fmaf(fc, cp.ifx, cp.ox), ryp = fmaf(fr, cp.ify, cp.oy);
+      const float rxq = fmaf(fc, cq.ifx, cq.ox), ryq = fmaf(fr, cq.ify, cq.oy);
+      float x[3], y[3];
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        x[i] = d[0][e] * fmaf(cp.R[3 * i], rxp, fmaf(cp.R[3 * i + 1], ryp, cp.R[3 * i + 2]));
+        y[i] = d[1][e] * fmaf(cq.R[3 * i], rxq, fmaf(cq.R[3 * i + 1], ryq, cq.R[3 * i + 2]));
+      }
+      const float c = d[2][e];
+      const bool fin = __builtin_isfinite(x[0] + x[1] + x[2] + y[0] + y[1] + y[2]) && __builtin_isfinite(c);
+      const bool valid = in && fin && c >= tau;
+      nvalid += valid ? 1 : 0;
+      nbad += (in && !fin) ? 1 : 0;
+      const float w = valid ? c : 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        x[i] = valid ? x[i] : 0.0f;
+        y[i] = valid ? y[i] : 0.0f;
+      }
+      const float wx0 = w * x[0], wx1 = w * x[1], wx2 = w * x[2];
+      const float wy0 = w * y[0], wy1 = w * y[1], wy2 = w * y[2];
+      a[0] += (double)w;  // the weight sum stays exact
+      s[1] += wx0; s[2] += wx1; s[3] += wx2;
+      s[4] += wy0; s[5] += wy1; s[6] += wy2;
+      s[7] = fmaf(wx0, x[0], fmaf(wx1, x[1], fmaf(wx2, x[2], s[7])));
+      s[8] = fmaf(wy0, x[0], s[8]);  s[9] = fmaf(wy0, x[1], s[9]);  s[10] = fmaf(wy0, x[2], s[10]);
+      s[11] = fmaf(wy1, x[0], s[11]); s[12] = fmaf(wy1, x[1], s[12]); s[13] = fmaf(wy1, x[2], s[13]);
+      s[14] = fmaf(wy2, x[0], s[14]); s[15] = fmaf(wy2, x[1], s[15]); s[16] = fmaf(wy2, x[2], s[16]);
+      if (rel0 + e >= lo_rel) L::advance(src, f, row, col);
+    }
+#pragma unroll
+    for (int j = 1; j < 17; ++j) a[j] += (double)s[j];
+  }
+  // to the submap frame: x = x' + tp, y = y' + tq
+  const double tp[3] = {cp.t[0], cp.t[1], cp.t[2]}, tq[3] = {cq.t[0], cq.t[1], cq.t[2]};
+  const double W = a[0], Sx[3] = {a[1], a[2], a[3]}, Sy[3] = {a[4], a[5], a[6]};
+  a[7] += 2.0 * (tp[0] * Sx[0] + tp[1] * Sx[1] + tp[2] * Sx[2]) + (tp[0] * tp[0] + tp[1] * tp[1] + tp[2] * tp[2]) * W;
+#pragma unroll
+  for (int i = 0; i < 3; ++i)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) a[8 + 3 * i + j] += tq[i] * Sx[j] + Sy[i] * tp[j] + tq[i] * tp[j] * W;
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    a[1 + i] += tp[i] * W;
+    a[4 + i] += tq[i] * W;
+  }
+}
+
 // Moments pass over one tile: FP64 products and per-lane FP64 sums (the
 // coordinates are uncentred here, so the second moments must keep more than
 // FP32 precision), integer counts, DPP wavefront reduction.
@@ -632,6 +710,15 @@ __device__ inline void tile_moments(const Shape& sh, const SrcCtx<DT>& pl, const
   int nvalid = 0, nbad = 0;
   const float tau = sh.tau;
   const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
+  if constexpr (DT == DT_DEPTH_F32 || DT == DT_DEPTH_BF16) {
+    if (pl.frame >= 0) {
+      tile_moments_depth_frame<DT, WG, ITEMS>(sh, pl, td, a, nvalid, nbad);
+      a[17] = (double)nvalid;
+      a[18] = (double)nbad;
+      block_store_f64<WG, NSTAT>(a, red, out);
+      return;
+    }
+  }
 #pragma unroll 1
   for (int it = 0; it < ITEMS; ++it) {
     const int rel0 = (it * WG + (int)threadIdx.x) * VEC;

@@ -844,7 +844,8 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
         double t = 0.0;
 #pragma unroll
         for (int c = 0; c < FB; ++c) t += Vi[c] * ys[k0 + c];
-        ys[k0 + tid] = t;  // one wavefront: every lane's reads precede the writes
+        wave_sync();  // the other lanes' reads of ys before this write
+        ys[k0 + tid] = t;
       }
       __syncthreads();
       for (int i = k0 + FB + tid; i < n; i += FIN_WG) {
@@ -872,7 +873,8 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
         double t = 0.0;
 #pragma unroll
         for (int r = 0; r < FB; ++r) t += Vi[r * FB + tid] * (ys[k0 + r] - red[r]);
-        ys[k0 + tid] = t;  // one wavefront: every lane's reads precede the writes
+        wave_sync();  // the other lanes' reads of ys before this write
+        ys[k0 + tid] = t;
       }
       __syncthreads();
     }
