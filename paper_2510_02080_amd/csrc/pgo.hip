@@ -125,7 +125,7 @@ constexpr int LIN_EDGES = 9;
 // v = psi A^T Om e follow in k_pgo_edge_M.
 __global__ __launch_bounds__(64) void k_pgo_linearize(PgoDev d, const s3a_sim3* __restrict__ Tm,
                                                      const double* __restrict__ omega, const s3a_sim3* __restrict__ T,
-                                                     double huber, int r2_only) {
+                                                     int r2_only) {
   __shared__ double aug[LIN_EDGES][7][14];
   const int lane = threadIdx.x, g = lane / 7, i = lane % 7;
   const int k = blockIdx.x * LIN_EDGES + g;
@@ -245,7 +245,7 @@ hipError_t launch_linearize(const PgoDev& d, const s3a_sim3* Tm, const double* o
                             int r2_only, hipStream_t st) {
   if (d.n_edges == 0) return hipSuccess;
   hipLaunchKernelGGL(k_pgo_linearize, dim3((d.n_edges + LIN_EDGES - 1) / LIN_EDGES), dim3(64), 0, st, d, Tm, omega, T,
-                     huber, r2_only);
+                     r2_only);
   if (!r2_only) {
     const int64_t nx = (int64_t)d.n_edges * 56;
     hipLaunchKernelGGL(k_pgo_edge_M, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st, d, omega, huber);
