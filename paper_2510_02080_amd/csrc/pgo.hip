@@ -78,6 +78,8 @@ struct PgoDev {
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
   const int32_t* chain; int32_t n_chain;
+  // breadth-first depth levels of the chain: entries [chain_lev[l], chain_lev[l+1]) have depth l + 1
+  const int32_t* chain_lev; int32_t n_chain_lev;
   // numeric storage
   double* Ld;     // [m][49] diagonal blocks (lower Cholesky factor after factorisation)
   double* Di;     // [m][49] inverses of the factored diagonal blocks of the sparse columns
@@ -98,15 +100,21 @@ struct PgoDev {
 __device__ inline Sim3d ld_pose(const s3a_sim3* p) { return load_sim3(p); }
 
 // Breadth-first chaining from the gauge node: T_j = T_i T_ij (dir 0) or
-// T_i = T_j T_ij^{-1} (dir 1). One lane; the order is a tree traversal.
-__global__ void k_pgo_chain(PgoDev d, const s3a_sim3* __restrict__ Tm, s3a_sim3* T) {
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  for (int k = 0; k < d.n_nodes; ++k) store_sim3(T + k, sim3_identity());
-  for (int c = 0; c < d.n_chain; ++c) {
-    const int nd = d.chain[4 * c], par = d.chain[4 * c + 1], e = d.chain[4 * c + 2], dir = d.chain[4 * c + 3];
-    const Sim3d Tp = ld_pose(T + par);
-    const Sim3d Te = ld_pose(Tm + e);
-    store_sim3(T + nd, dir == 0 ? sim3_compose(Tp, Te) : sim3_compose(Tp, sim3_inverse(Te)));
+// T_i = T_j T_ij^{-1} (dir 1), one workgroup, the entries of one depth level in
+// parallel (each depends only on a parent of the level before).
+constexpr int CHAIN_WG = 256;
+__global__ __launch_bounds__(CHAIN_WG) void k_pgo_chain(PgoDev d, const s3a_sim3* __restrict__ Tm, s3a_sim3* T) {
+  const int tid = threadIdx.x;
+  for (int k = tid; k < d.n_nodes; k += CHAIN_WG) store_sim3(T + k, sim3_identity());
+  __syncthreads();
+  for (int l = 0; l < d.n_chain_lev; ++l) {
+    for (int c = d.chain_lev[l] + tid; c < d.chain_lev[l + 1]; c += CHAIN_WG) {
+      const int nd = d.chain[4 * c], par = d.chain[4 * c + 1], e = d.chain[4 * c + 2], dir = d.chain[4 * c + 3];
+      const Sim3d Tp = ld_pose(T + par);
+      const Sim3d Te = ld_pose(Tm + e);
+      store_sim3(T + nd, dir == 0 ? sim3_compose(Tp, Te) : sim3_compose(Tp, sim3_inverse(Te)));
+    }
+    __syncthreads();
   }
 }
 
@@ -920,7 +928,7 @@ struct Symbolic {
   int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
       up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk,
-      chain, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b;
+      chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b;
   std::vector<int8_t> gv_sign;
 };
 
@@ -1127,6 +1135,7 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
     inc[ij[2 * k + 1]].push_back(k);
   }
   std::vector<char> placed(n, 0);
+  std::vector<int> depth(n, 0);
   placed[gauge] = 1;
   std::deque<int> q{gauge};
   while (!q.empty()) {
@@ -1136,15 +1145,24 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
       const int i = ij[2 * k], j = ij[2 * k + 1];
       if (i == a && !placed[j]) {
         placed[j] = 1;
+        depth[j] = depth[a] + 1;
         S.chain.insert(S.chain.end(), {j, i, k, 0});
         q.push_back(j);
       } else if (j == a && !placed[i]) {
         placed[i] = 1;
+        depth[i] = depth[a] + 1;
         S.chain.insert(S.chain.end(), {i, j, k, 1});
         q.push_back(i);
       }
     }
   }
+  // breadth-first order is nondecreasing in depth: level boundaries of the chain
+  S.chain_lev.assign(1, 0);
+  for (size_t c = 0; c < S.chain.size() / 4; ++c) {
+    const int dep = depth[S.chain[4 * c]];
+    while ((int)S.chain_lev.size() < dep) S.chain_lev.push_back((int32_t)c);
+  }
+  S.chain_lev.push_back((int32_t)(S.chain.size() / 4));
   return S;
 }
 
@@ -1357,7 +1375,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
     total += bytes_of<int32_t>(S.fu_ptr.size()) + bytes_of<int32_t>(S.fu_a.size() + 1) * 2;
     total += bytes_of<int32_t>(S.bs_ptr.size()) + bytes_of<int32_t>(S.bs_blk.size() + 1);
-    total += bytes_of<int32_t>(S.chain.size() + 4);
+    total += bytes_of<int32_t>(S.chain.size() + 4) + bytes_of<int32_t>(S.chain_lev.size());
     total += bytes_of<double>(49 * (size_t)m) * 2 + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<double>(iters_cap) + bytes_of<int32_t>(4);
@@ -1423,6 +1441,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_bsb = carve<int32_t>(c, S.bs_blk.size() + 1); put(p_bsb, S.bs_blk); d.bs_blk = p_bsb;
     int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
     d.n_chain = (int32_t)(S.chain.size() / 4);
+    int32_t* p_cl = carve<int32_t>(c, S.chain_lev.size()); put(p_cl, S.chain_lev); d.chain_lev = p_cl;
+    d.n_chain_lev = (int32_t)S.chain_lev.size() - 1;
     d.Ld = carve<double>(c, 49 * (size_t)m);
     d.Di = carve<double>(c, 49 * (size_t)m);
     d.Lb = carve<double>(c, 49 * (size_t)nb + 49);
@@ -1464,7 +1484,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
   hipError_t e = launch_fill_zero(reinterpret_cast<uint32_t*>(d.status), 1, st);
   if (e != hipSuccess) return fail(last_hip, e);
   if (p.flags & S3A_PGO_INIT_CHAIN) {
-    hipLaunchKernelGGL(k_pgo_chain, dim3(1), dim3(64), 0, st, d, T_meas, T);
+    hipLaunchKernelGGL(k_pgo_chain, dim3(1), dim3(CHAIN_WG), 0, st, d, T_meas, T);
     if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
   }
   if (p.flags & S3A_PGO_LM) return pgo_solve_lm(ws, last_hip, n_nodes, n_edges, T_meas, omega, T, p, report, st);
