@@ -60,13 +60,14 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
       if (rel0 >= end_rel) break;
       float v[7][VEC];
       Planes<DT>::load(SrcCtx<DT>{pl}, td.begin + rel0, sh.n_points, v);
-#pragma unroll 1
+#pragma unroll
       for (int e = 0; e < VEC; ++e) {
         float x[7];
 #pragma unroll
         for (int j = 0; j < 7; ++j) x[j] = v[j][e];
         const bool valid = P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
-        if (!valid) continue;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;  // masked points add zeros
         double y[3], r[3];
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -75,9 +76,9 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
         }
         const double c = x[6];
         const double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const double en = sqrt(e2);
-        const bool outl = en > delta;
-        const double psi = outl ? delta / en : 1.0;
+        const double ie = rsqrt(e2);  // 1 / |r|, used only outside delta (|r| > delta > 0)
+        const bool outl = e2 > delta * delta;
+        const double psi = outl ? delta * ie : 1.0;
         const double om = c * psi;
         a[0] += om;
 #pragma unroll
@@ -90,8 +91,8 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
         for (int i = 0; i < 3; ++i)
 #pragma unroll
           for (int j = 0; j < 3; ++j) a[13 + 3 * i + j] = fma(om * y[i], r[j], a[13 + 3 * i + j]);
-        // rank-one correction of the Huber Hessian outside delta
-        const double k1 = outl ? c * psi / e2 : 0.0;
+        // rank-one correction of the Huber Hessian outside delta: c psi / e^2 u u^T
+        const double k1 = outl ? om * ie * ie : 0.0;
         const double u[7] = {r[0], r[1], r[2], y[1] * r[2] - y[2] * r[1], y[2] * r[0] - y[0] * r[2],
                              y[0] * r[1] - y[1] * r[0], y[0] * r[0] + y[1] * r[1] + y[2] * r[2]};
 #pragma unroll
@@ -101,7 +102,7 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
           for (int j = 0; j <= i; ++j) a[22 + i * (i + 1) / 2 + j] = fma(ku, u[j], a[22 + i * (i + 1) / 2 + j]);
         }
         a[50] += c;
-        a[51] += 1.0;
+        a[51] += valid ? 1.0 : 0.0;
       }
     }
     block_store_h<WG>(a, red, hpart + (int64_t)t * HSTAT);
