@@ -34,6 +34,12 @@
  *     stream before returning.
  *   - A handle owns its workspace (grown on demand), captured graphs and
  *     autotuning results. A handle must not be used by two threads at once.
+ *   - Calls through one handle share that workspace, so they execute in the
+ *     order they were issued, whatever streams they are given: a call on a
+ *     stream other than the previous call's makes its stream wait (on the
+ *     device, hipStreamWaitEvent) for all work of the previous call. Work
+ *     through one handle therefore never overlaps; for concurrent work on
+ *     several streams, use one handle per stream.
  *
  * Errors
  *   - Every call returns S3A_OK (0) or a negative code (s3a_strerror).
@@ -43,7 +49,11 @@
  *     S3A_ENOMEM: workspace allocation failed.
  *   - Problems of one pair do not fail the call: they are reported in that
  *     pair's status (S3A_PAIR_*), and the pair's outputs are the identity with
- *     cost NaN. Other pairs are unaffected.
+ *     cost NaN. Other pairs are unaffected, with one exception: invalid
+ *     offsets (any offsets[k] > offsets[k+1], or any offset outside
+ *     [0, n_points]) are detected on the device and mark EVERY pair of the
+ *     call S3A_PAIR_BADRANGE, since the work split over tiles is derived from
+ *     the whole offsets array.
  */
 #ifndef S3A_H
 #define S3A_H
@@ -75,7 +85,7 @@ enum {
   S3A_PAIR_EMPTY = 1,      /* no valid point (or all weights zero with tau = 0) */
   S3A_PAIR_DEGENERATE = 2, /* coincident or collinear points, or a non-SPD normal matrix */
   S3A_PAIR_NONFINITE = 3,  /* no valid point and some were dropped for NaN/Inf, or a non-finite solve */
-  S3A_PAIR_BADRANGE = 4,   /* offsets[k] > offsets[k+1], or outside [0, n_points] */
+  S3A_PAIR_BADRANGE = 4,   /* the call's offsets are invalid (every pair gets it), or a depth pair's geometry is */
   S3A_PAIR_ABORTED = 5     /* the batched launch stopped waiting for this pair (internal error) */
 };
 

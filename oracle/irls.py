@@ -67,8 +67,9 @@ def point_jacobians(y):
     return J
 
 
-def gn_system(T, p, q, w, delta):
-    """H, g, L, inlier count of the IRLS-weighted GN system at T (valid points)."""
+def gn_system(T, p, q, w, delta, return_e=False):
+    """H, g, L, inlier count of the IRLS-weighted GN system at T (valid points);
+    with return_e also the residual norms e_i."""
     y = sim3.act(T, p)
     r = y - q
     e = np.linalg.norm(r, axis=1)
@@ -78,6 +79,8 @@ def gn_system(T, p, q, w, delta):
     H = np.einsum('n,nai,naj->ij', om, J, J)
     g = np.einsum('n,nai,na->i', om, J, r)
     L = float((w * huber_rho(e, delta)).sum())
+    if return_e:
+        return H, g, L, int((e <= delta).sum()), e
     return H, g, L, int((e <= delta).sum())
 
 
@@ -90,7 +93,8 @@ def _failed(status, V, C, n_nonfinite, iters):
     return dict(status=status, T=np.eye(4), s=1.0, R=np.eye(3), t=np.zeros(3),
                 V=V, C=C, n_nonfinite=n_nonfinite, costs=[np.nan] * iters,
                 inliers=[0] * iters, final_cost=np.nan, final_inliers=0,
-                H=np.full((7, 7), np.nan), g=np.full(7, np.nan), T0=np.eye(4))
+                H=np.full((7, 7), np.nan), g=np.full(7, np.nan), T0=np.eye(4),
+                e_lin=np.zeros(0, np.float32), delta=np.nan)
 
 
 def irls_align(p, q, c, tau=0.0, delta=0.05, iters=10, init=None):
@@ -98,7 +102,9 @@ def irls_align(p, q, c, tau=0.0, delta=0.05, iters=10, init=None):
 
     Returns a dict with the final similarity (T, s, R, t), status, V, C, the cost
     and inlier count at each linearisation point (costs[k], inliers[k] at S_k),
-    the cost at the final iterate, and H, g of the last GN system.
+    the cost at the final iterate, H, g of the last GN system, and the valid
+    points' residual norms at the last linearisation point (e_lin, rounded to
+    FP32: a diagnostic for how many points lie near the Huber threshold).
     """
     p = np.asarray(p, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
@@ -124,8 +130,10 @@ def irls_align(p, q, c, tau=0.0, delta=0.05, iters=10, init=None):
     costs, inliers = [], []
     H = np.full((7, 7), np.nan)
     g = np.full(7, np.nan)
+    e_lin = np.zeros(0, np.float32)
     for _ in range(iters):
-        H, g, L, nin = gn_system(T, pv, qv, w, delta)
+        H, g, L, nin, e = gn_system(T, pv, qv, w, delta, return_e=True)
+        e_lin = e.astype(np.float32)
         costs.append(L)
         inliers.append(nin)
         try:
@@ -138,7 +146,8 @@ def irls_align(p, q, c, tau=0.0, delta=0.05, iters=10, init=None):
     s, R, t = sim3.to_srt(T)
     return dict(status=STATUS_OK, T=T, s=s, R=R, t=t, V=V, C=C,
                 n_nonfinite=n_nonfinite, costs=costs, inliers=inliers,
-                final_cost=final_cost, final_inliers=final_inliers, H=H, g=g, T0=T0)
+                final_cost=final_cost, final_inliers=final_inliers, H=H, g=g, T0=T0,
+                e_lin=e_lin, delta=float(delta))
 
 
 def align_batch(p, q, c, offsets, tau=0.0, delta=0.05, iters=10, pairs=None):

@@ -4,16 +4,18 @@ FP64 per-pair math, for CPU tests) in-tree."""
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 HIP_SOURCES = ["api.hip", "align.hip", "adjoint.hip", "persistent.hip", "pgo.hip", "points.hip", "implicit.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
              "-I" + os.path.join(ROOT, "include"), "-I" + CSRC]
+OBJ_DIR = os.path.join(HERE, "_build")
 
 
 def run(cmd):
@@ -27,9 +29,18 @@ def run(cmd):
 
 
 def build(verbose=False):
+    """Compile every HIP source (each translation unit holds its kernels and
+    their launches, so no relocatable device code is needed) in parallel, then
+    link the shared library."""
     out = os.path.join(HERE, "libs3a.so")
     tmp = out + ".tmp"
-    run([HIPCC] + HIP_FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in HIP_SOURCES])
+    os.makedirs(OBJ_DIR, exist_ok=True)
+    objs = [os.path.join(OBJ_DIR, os.path.splitext(src)[0] + ".o") for src in HIP_SOURCES]
+    jobs = [[HIPCC] + HIP_FLAGS + ["-c", "-o", o, os.path.join(CSRC, src)] for src, o in zip(HIP_SOURCES, objs)]
+    workers = max(1, min(len(jobs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(run, jobs))
+    run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, out)
     host = os.path.join(HERE, "libs3a_hostmath.so")
     run(["g++", "-O2", "-std=c++17", "-fPIC", "-shared", "-Wall", "-o", host + ".tmp",

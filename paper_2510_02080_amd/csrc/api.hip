@@ -62,6 +62,10 @@ struct s3a_handle {
   int32_t* flags_dev = nullptr;  // small device scratch (offset-check flag of the point transform)
   double* hpart = nullptr;       // per-tile sums of the implicit-derivative pass
   int64_t hpart_tiles = 0;
+  // issue order of calls across streams (they share the workspace)
+  hipEvent_t order_ev = nullptr;
+  hipStream_t order_stream = nullptr;
+  bool order_valid = false;
 };
 
 namespace {
@@ -99,6 +103,34 @@ struct TimedLaunch {
     h->ev_used.push_back(ev);
   }
 };
+
+// Calls through one handle share its workspace (descriptor slot, tile table,
+// partials, per-pair state), so they must run in issue order. A call on a
+// stream other than the previous call's first makes its stream wait, on the
+// device, for everything the previous call enqueued; on leaving, it records
+// where its own work ends. Calls on one stream are ordered by the stream.
+struct StreamOrder {
+  s3a_handle* h;
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+  StreamOrder(s3a_handle* hh, hipStream_t s) : h(hh), st(s) {
+    if (h->order_valid && h->order_stream != st) err = hipStreamWaitEvent(st, h->order_ev, 0);
+  }
+  ~StreamOrder() {
+    if (hipEventRecord(h->order_ev, st) == hipSuccess) {
+      h->order_stream = st;
+      h->order_valid = true;
+    } else {
+      // no marker for this call's end: drain it instead, so no later call can overtake it
+      (void)hipStreamSynchronize(st);
+      h->order_valid = false;
+    }
+  }
+};
+
+#define S3A_ORDERED(h, st)              \
+  StreamOrder order_(h, st);            \
+  if (order_.err != hipSuccess) return hip_fail(h, order_.err)
 
 struct DeviceGuard {
   int prev = -1;
@@ -335,6 +367,12 @@ int s3a_create(s3a_handle** out, int device) {
     delete h;
     return S3A_EHIP;
   }
+  e = hipEventCreateWithFlags(&h->order_ev, hipEventDisableTiming);
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(h->capture_stream);
+    delete h;
+    return S3A_EHIP;
+  }
   *out = h;
   return S3A_OK;
 }
@@ -351,6 +389,7 @@ int s3a_destroy(s3a_handle* h) {
   for (auto& ev : h->ev_used) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   for (auto& ev : h->ev_free) { (void)hipEventDestroy(ev.first); (void)hipEventDestroy(ev.second); }
   if (h->capture_stream) (void)hipStreamDestroy(h->capture_stream);
+  if (h->order_ev) (void)hipEventDestroy(h->order_ev);
   delete h;
   return S3A_OK;
 }
@@ -367,6 +406,7 @@ int align_run(s3a_handle* h, const s3a_align_desc* d, const s3a_depth_pair* dept
   int rc = S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
   const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
   const Shape sh = make_shape(d, lc);
   const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
@@ -512,6 +552,7 @@ int s3a_align_cost(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* S, co
   if (d->n_pairs == 0) return S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
   const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
   const Shape sh = make_shape(d, lc);
   const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
@@ -548,6 +589,7 @@ int s3a_align_pairs_backward(s3a_handle* h, const s3a_align_desc* d, const s3a_s
   if (d->n_pairs == 0) return S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
   const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
   const Shape sh = make_shape(d, lc);
   const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
@@ -588,6 +630,7 @@ int s3a_align_pairs_implicit_backward(s3a_handle* h, const s3a_align_desc* d, co
   if (d->n_pairs == 0) return S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
   const LaunchCfg lc = pick_cfg(h, d->dtype, d->n_points);
   const Shape sh = make_shape(d, lc);
   const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
@@ -677,6 +720,7 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   if (d->n_pairs == 0) return S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
   // scratch outputs
   s3a_sim3* S = nullptr;
   S3A_TRY(hipMalloc(&S, sizeof(s3a_sim3) * d->n_pairs));
@@ -759,6 +803,7 @@ int s3a_transform_points(s3a_handle* h, int32_t dtype, int64_t n_points, int32_t
     if (((uintptr_t)q & 15) != 0) return S3A_EINVAL;
   DeviceGuard g(h->device);
   hipStream_t st = (hipStream_t)stream;
+  S3A_ORDERED(h, st);
   if (!h->flags_dev) S3A_TRY(hipMalloc(&h->flags_dev, 256));
   S3A_TRY(launch_check_offsets(n_points, n_submaps, offsets, h->flags_dev, status, st));
   TimedLaunch tl(h, st);
@@ -775,6 +820,7 @@ int s3a_correct_points(s3a_handle* h, int64_t n_corr, const int64_t* src, const 
   if (n_sparse > 0 && (!sx || !sy || !sz)) return S3A_EINVAL;
   DeviceGuard g(h->device);
   hipStream_t st = (hipStream_t)stream;
+  S3A_ORDERED(h, st);
   TimedLaunch tl(h, st);
   S3A_TRY(launch_correct(n_corr, src, dst, n_world, wx, wy, wz, n_sparse, sx, sy, sz, n_skipped, st));
   return S3A_OK;
@@ -785,8 +831,9 @@ int s3a_pose_graph_solve(s3a_handle* h, int32_t n_nodes, int32_t n_edges, const 
                          s3a_stream stream) {
   if (!h) return S3A_EINVAL;
   DeviceGuard g(h->device);
-  return pgo_solve(&h->pgo, &h->last_hip, n_nodes, n_edges, ij, T_meas, omega, T, params, report,
-                   static_cast<hipStream_t>(stream));
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
+  return pgo_solve(&h->pgo, &h->last_hip, n_nodes, n_edges, ij, T_meas, omega, T, params, report, st);
 }
 
 }  // extern "C"

@@ -25,7 +25,12 @@ DR = 8 * 2.0 ** -24 * EXTENT
 def ragged_batch(sizes, seed=0, tau=1.5, outlier_frac=0.1, specials=None):
     """Pairs of the given point counts, frustum geometry as the config-0 recipe
     with log-normal confidences. specials: {k: kind} with kind in
-    'nan_all', 'nan_some', 'below_tau', 'collinear', 'coincident'."""
+    'nan_all', 'nan_some', 'below_tau', 'collinear', 'coincident',
+    'planar' (source points on a tilted plane: a wall or a floor; the
+    cross-covariance has rank 2 up to rounding, so the closed form's third
+    direction comes from the determinant sign alone) and 'reflected' (targets
+    are a mirror image of the source: the best proper rotation is the
+    reflection-corrected one, and the Huber steps start far from any fit)."""
     rng = np.random.default_rng(seed)
     specials = specials or {}
     pairs = []
@@ -50,6 +55,16 @@ def ragged_batch(sizes, seed=0, tau=1.5, outlier_frac=0.1, specials=None):
             q = s * p @ R.T + t
         elif kind == "coincident":
             p[:] = p[0]
+        elif kind == "planar":
+            e = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+            p = np.array([0.5, -0.3, 5.0]) + rng.uniform(-3, 3, (n, 2)) @ e[:2]
+            q = synth.pointmaps.make_targets(rng, p, s, R, t, outlier_frac=outlier_frac)
+        elif kind == "reflected":
+            # distinct spreads along x, y, z, so the corrected rotation is unique;
+            # the mirror flips y, the direction of least spread
+            p = np.c_[rng.uniform(-3, 3, n), rng.uniform(-1, 1, n), rng.uniform(1, 10, n)]
+            q = synth.pointmaps.make_targets(rng, p * np.array([1.0, -1.0, 1.0]), s, R, t,
+                                             outlier_frac=outlier_frac)
         pairs.append((p, q, c, (s, R, t)))
     return synth.make_batch(pairs, tau=tau)
 
@@ -57,6 +72,17 @@ def ragged_batch(sizes, seed=0, tau=1.5, outlier_frac=0.1, specials=None):
 def srt_of(T):
     s = np.cbrt(np.linalg.det(T[:3, :3]))
     return s, T[:3, :3] / s, T[:3, 3]
+
+
+def inlier_band(ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), dr=DR):
+    """How many inliers a correct GPU result may count differently from the
+    oracle at the last linearisation point S_{K-1}: the points whose residual
+    norm lies within the GPU's possible deviation of the Huber threshold.
+    That deviation is the FP32 residual rounding dr plus what a pose within the
+    tolerances moves a model point of the scene (rotation and scale act on
+    points up to EXTENT from the origin, translation relative to max(|t|, 1 m))."""
+    band = dr + (tol[0] + tol[1]) * EXTENT + tol[2] * max(float(np.linalg.norm(ref["t"])), 1.0)
+    return int(np.count_nonzero(np.abs(ref["e_lin"].astype(np.float64) - ref["delta"]) <= band))
 
 
 def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where="", dr=DR):
@@ -76,7 +102,8 @@ def check_pair(T_gpu, info, ref, tol=(TOL_ROT, TOL_SCALE, TOL_TRANS), where="", 
     if K:
         L = ref["costs"][-1]
         assert abs(info["cost"] - L) <= 1e-5 * abs(L) + np.sqrt(2 * abs(L)) * dr, where
-        assert abs(int(info["n_inliers"]) - ref["inliers"][-1]) <= max(3, 1e-4 * ref["V"]), where
+        d_in = abs(int(info["n_inliers"]) - ref["inliers"][-1])
+        assert d_in <= inlier_band(ref, tol, dr), f"{where}: inliers {info['n_inliers']} vs {ref['inliers'][-1]}"
         Hr = ref["H"] / 1.0
         Hu = Hr[np.triu_indices(7)]
         sc = np.abs(Hr).max()

@@ -42,8 +42,9 @@ def test_config0(h, flags):
 
 
 SIZES = [5000, 0, 1, 2, 3, 7, 100, 2047, 2048, 2049, 4096, 4097, 8191, 30001, 65537, 3000, 3000, 3000, 3000,
-         3000, 20000]
-SPECIALS = {15: "nan_all", 16: "nan_some", 17: "below_tau", 18: "collinear", 19: "coincident"}
+         3000, 20000, 30000, 30000]
+SPECIALS = {15: "nan_all", 16: "nan_some", 17: "below_tau", 18: "collinear", 19: "coincident", 21: "planar",
+            22: "reflected"}
 
 
 @pytest.mark.parametrize("flags", [0, s3a.FLAG_PLAIN, s3a.FLAG_FINAL_COST, s3a.FLAG_PERSISTENT | s3a.FLAG_FINAL_COST])
@@ -62,6 +63,7 @@ def test_ragged_and_degenerate(h, flags):
     st = info["status"]
     assert st[1] == s3a.PAIR_EMPTY and st[2] == s3a.PAIR_DEGENERATE and st[15] == s3a.PAIR_NONFINITE
     assert st[17] == s3a.PAIR_EMPTY and st[18] == s3a.PAIR_DEGENERATE and st[19] == s3a.PAIR_DEGENERATE
+    assert st[21] == s3a.PAIR_OK and st[22] == s3a.PAIR_OK
 
 
 @pytest.mark.parametrize("K", [0, 1, 3])
@@ -157,3 +159,33 @@ def test_grid_size_does_not_change_bits(h):
             h.set_tuning(s3a.F32)
     assert np.array_equal(np.asarray(out[0][0]), np.asarray(out[1][0]))
     assert out[0][1].tobytes() == out[1][1].tobytes()
+
+
+def test_calls_on_two_streams(h):
+    """One handle, calls on two streams: they share the handle's workspace, so
+    the library orders the second after the first (both correct); two handles
+    on two streams run independently (both correct). The two batches have the
+    same shape (sizes, offsets), so the calls differ only in values."""
+    sizes = [150000, 3000, 60000]
+    b1 = ragged_batch(sizes, seed=51)
+    b2 = ragged_batch(sizes, seed=52)
+    pm1 = s3a.Pointmaps.from_batch(b1, "cuda:0")
+    pm2 = s3a.Pointmaps.from_batch(b2, "cuda:0")
+    h2 = s3a.Handle(0)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    results = {}
+    for mode, hb in (("one handle", h), ("two handles", h2)):
+        for flags in (0, s3a.FLAG_NO_GRAPH):
+            with torch.cuda.stream(s1):
+                Sa, ia = h.align_pairs(pm1, b1.tau, b1.delta, b1.iters, flags=flags)
+            with torch.cuda.stream(s2):
+                Sb, ib = hb.align_pairs(pm2, b2.tau, b2.delta, b2.iters, flags=flags)
+            torch.cuda.synchronize()
+            results[(mode, flags)] = ((b1, Sa, ia), (b2, Sb, ib))
+    for key, outs in results.items():
+        for b, S, ibuf in outs:
+            T, info = s3a.sim3_to_numpy(S), s3a.info_to_numpy(ibuf)
+            for k in range(b.n_pairs):
+                p, q, c = b.decoded_pair(k)
+                check_pair(T[k], info[k], irls.irls_align(p, q, c, b.tau, b.delta, b.iters), where=f"{key} pair {k}")

@@ -33,8 +33,9 @@ def h():
 
 
 def test_bf16_ragged_and_degenerate(h):
-    sizes = [3000, 0, 2, 9999, 4096, 4097, 70001, 3000, 3000]
-    b = ragged_batch(sizes, seed=21, specials={7: "nan_some", 8: "collinear"}).to_bf16()
+    sizes = [3000, 0, 2, 9999, 4096, 4097, 70001, 3000, 3000, 30000, 30000]
+    b = ragged_batch(sizes, seed=21, specials={7: "nan_some", 8: "collinear", 9: "planar",
+                                               10: "reflected"}).to_bf16()
     pm = s3a.Pointmaps.from_batch(b, "cuda:0")
     S, ib = h.align_pairs(pm, b.tau, b.delta, b.iters)
     torch.cuda.synchronize()
@@ -42,6 +43,7 @@ def test_bf16_ragged_and_degenerate(h):
     for k in range(b.n_pairs):
         p, q, c = b.decoded_pair(k)
         check_pair(T[k], info[k], irls.irls_align(p, q, c, b.tau, b.delta, b.iters), where=f"bf16 pair {k}")
+    assert info["status"][9] == s3a.PAIR_OK and info["status"][10] == s3a.PAIR_OK
 
 
 def test_bf16_vs_fp32_originals(h):
