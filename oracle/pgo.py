@@ -10,7 +10,7 @@ start from chaining the relative transforms.
 
 Readings where the section is silent (it names Levenberg-Marquardt in a
 third-party library without its settings, and leaves Omega unspecified):
-* Omega_ij = I_7 unless given.
+* Omega_ij = I_7 unless given; from a pairwise alignment, ``edge_information``.
 * pgo_solve: Gauss-Newton, optional fixed damping lambda (H + lambda diag(H));
   no line search, exactly ``iters`` steps.
 * pgo_solve_lm: Levenberg-Marquardt with Marquardt's diagonal scaling and
@@ -56,6 +56,25 @@ def chain_init(n_nodes, edges, T_meas, gauge=0):
                 placed[i] = True
                 queue.append(i)
     return np.array(T)
+
+
+def edge_information(S, H, n_valid, info_scale):
+    """Information matrix of the edge a pairwise alignment gives (Sec. III-C.2's
+    registration result becoming a Sec. III-E edge; the section leaves Omega
+    open). Aligning source points of submap j onto target points of submap i
+    returns S, the edge's measurement T_ij = S, together with H, the
+    Gauss-Newton matrix of the alignment cost for left perturbations
+    S -> Exp(xi) S (normalised weights). A relative pose T = Exp(xi) S has the
+    edge residual e = Log(S^-1 T) = Log(Exp(Ad(S^-1) xi)) = Ad(S^-1) xi, so the
+    cost's quadratic model 1/2 xi^T H xi equals 1/2 e^T Ad(S)^T H Ad(S) e.
+    Scaled by the valid-point count and info_scale (1/sigma^2 for points with
+    isotropic noise sigma, weights uniform), that is the estimate's inverse
+    covariance:
+
+        Omega = info_scale * n_valid * Ad(S)^T H Ad(S).
+    """
+    A = sim3.Ad(S)
+    return float(info_scale) * float(n_valid) * (A.T @ np.asarray(H, dtype=np.float64) @ A)
 
 
 def edge_residual(Ti, Tj, Tij):

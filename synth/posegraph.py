@@ -12,10 +12,12 @@
   similarity (``noisy_measurements``), for solver-only checks.
 """
 
+import mmap
+
 import numpy as np
 from scipy.spatial.transform import Rotation
 
-from .pointmaps import SEED_BASE, pair_from_frames
+from .pointmaps import PLANES, SEED_BASE, Batch, pair_from_frames
 
 
 def _mat(s, R, t):
@@ -76,3 +78,47 @@ def edge_pair(T, edge, k, H=392, W=518, seed=4):
     i, j = edge
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([SEED_BASE + seed, 1, k])))
     return pair_from_frames(rng, H, W, T=_srt(np.linalg.inv(T[i]) @ T[j]))
+
+
+_EDGE_JOB = {}
+
+
+def _fill_edge(k):
+    """Generate edge pair k into the shared planes (runs in a forked worker)."""
+    job = _EDGE_JOB
+    p, q, c, _ = edge_pair(job["T"], job["edges"][k], k, job["H"], job["W"], job["seed"])
+    a = k * job["H"] * job["W"]
+    b = a + len(p)
+    pl = job["planes"]
+    for d, nm in enumerate(("px", "py", "pz")):
+        pl[nm][a:b] = p[:, d]
+    for d, nm in enumerate(("qx", "qy", "qz")):
+        pl[nm][a:b] = q[:, d]
+    pl["c"][a:b] = c
+    return k
+
+
+def edge_batch(T, edges, H=392, W=518, seed=4, tau=1.5, delta=0.05, iters=10, workers=1):
+    """All edge pairs of a graph as one FP32 SoA batch (pair k = edge k, H x W
+    points each, ``edge_pair``'s recipe). The ground truth of pair k is
+    T_i^{-1} T_j. workers > 1 generates the pairs in forked processes that
+    write straight into planes in anonymous shared memory."""
+    E = len(edges)
+    n = E * H * W
+    offsets = np.arange(E + 1, dtype=np.int64) * (H * W)
+    buf = mmap.mmap(-1, max(1, 4 * n * len(PLANES)))
+    planes = {nm: np.frombuffer(buf, dtype=np.float32, count=n, offset=4 * n * j) for j, nm in enumerate(PLANES)}
+    _EDGE_JOB.update(T=T, edges=np.asarray(edges), H=H, W=W, seed=seed, planes=planes)
+    try:
+        if workers > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(workers) as pool:
+                for _ in pool.imap_unordered(_fill_edge, range(E), chunksize=4):
+                    pass
+        else:
+            for k in range(E):
+                _fill_edge(k)
+    finally:
+        _EDGE_JOB.clear()
+    gt = [_srt(np.linalg.inv(T[i]) @ T[j]) for i, j in edges]
+    return Batch(planes, offsets, "f32", tau, delta, iters, gt, "edges")
