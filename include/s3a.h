@@ -322,6 +322,32 @@ int s3a_pose_graph_solve(s3a_handle* h, int32_t n_nodes, int32_t n_edges, const 
                          const s3a_pgo_params* params, s3a_pgo_report* report, s3a_stream stream);
 
 /*
+ * Pose-graph edges from pairwise alignments (Sec. III-C.2's registration result
+ * becomes a Sec. III-E edge; the paper leaves the information matrix open).
+ * Pair e of an s3a_align_pairs call aligned source points of submap j onto
+ * target points of submap i; its result S_e is the edge's measurement
+ * T_ij = S_e, and its last Gauss-Newton matrix H_e (s3a_align_info.H, for left
+ * perturbations S -> Exp(xi) S, normalised weights) gives the information
+ *   Omega_e = info_scale * n_valid_e * Ad(S_e)^T H_e Ad(S_e),
+ * since a relative pose T = Exp(xi) S_e has edge residual
+ * e = Log(S_e^-1 T) = Ad(S_e^-1) xi, so 1/2 xi^T H xi = 1/2 e^T Ad^T H Ad e.
+ * With info_scale = 1/sigma^2 that is the inverse covariance of an alignment
+ * of n_valid equally weighted points with isotropic noise sigma.
+ *   n_edges:     pairs (>= 0); pair e gives edge e.
+ *   S, info:     device, n_edges each: s3a_align_pairs' outputs.
+ *   info_scale:  > 0 and finite.
+ *   T_meas:      device, n_edges similarities (may be S itself: in place).
+ *   omega:       device, 49 * n_edges doubles, row-major 7x7, symmetric.
+ *   edge_status: device, n_edges int32 (the pair's status), or NULL. A failed
+ *                pair (status != S3A_PAIR_OK) gives T_meas = identity and
+ *                Omega = 0: the edge then adds nothing to the pose graph.
+ * The outputs feed s3a_pose_graph_solve's T_meas and omega directly.
+ */
+int s3a_edges_from_alignment(s3a_handle* h, int32_t n_edges, const s3a_sim3* S, const s3a_align_info* info,
+                             double info_scale, s3a_sim3* T_meas, double* omega, int32_t* edge_status,
+                             s3a_stream stream);
+
+/*
  * Launch shape of the alignment kernels. The autotuner picks one per
  * (dtype, batch size class) by timing candidates on the caller's data;
  * s3a_set_tuning forces one (for tests and sweeps).

@@ -85,6 +85,8 @@ _EXPORTS = {
                                                          ctypes.c_uint32] + [c_void_p] * 9 + [c_void_p]),
     "s3a_align_depth_pairs": (ctypes.c_int, [c_void_p, ctypes.POINTER(DepthDesc), c_void_p, c_void_p, c_void_p,
                                              c_void_p]),
+    "s3a_edges_from_alignment": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_double,
+                                                c_void_p, c_void_p, c_void_p, c_void_p]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -340,6 +342,22 @@ class Handle:
                                              _ptr(omega), _ptr(T), ctypes.byref(p), ctypes.byref(rep),
                                              _stream(T_meas.device)), self.h)
         return T, rep
+
+    def edges_from_alignment(self, S, info, info_scale, T_meas=None, omega=None, status=None):
+        """Pose-graph edges from an alignment batch: S (E, 16) float64 and the
+        info buffer of align_pairs (device). Returns (T_meas (E, 16), omega
+        (E, 49) float64, status (E,) int32), all on the device."""
+        n = int(S.shape[0])
+        dev = S.device
+        if T_meas is None:
+            T_meas = torch.empty((n, SIM3_DOUBLES), dtype=torch.float64, device=dev)
+        if omega is None:
+            omega = torch.empty((n, 49), dtype=torch.float64, device=dev)
+        if status is None:
+            status = torch.empty(n, dtype=torch.int32, device=dev)
+        _check(self.lib.s3a_edges_from_alignment(self.h, n, _ptr(S), _ptr(info), float(info_scale), _ptr(T_meas),
+                                                 _ptr(omega), _ptr(status), _stream(dev)), self.h)
+        return T_meas, omega, status
 
     def transform_points(self, xyz, offsets, T, out=None, status=None):
         """Point correction, step 1. xyz: (3, N) device tensor, FP32 or BF16

@@ -826,6 +826,20 @@ int s3a_correct_points(s3a_handle* h, int64_t n_corr, const int64_t* src, const 
   return S3A_OK;
 }
 
+int s3a_edges_from_alignment(s3a_handle* h, int32_t n_edges, const s3a_sim3* S, const s3a_align_info* info,
+                             double info_scale, s3a_sim3* T_meas, double* omega, int32_t* edge_status,
+                             s3a_stream stream) {
+  if (!h || n_edges < 0) return S3A_EINVAL;
+  if (!(info_scale > 0.0) || !(info_scale < __builtin_inf())) return S3A_EINVAL;
+  if (n_edges > 0 && (!S || !info || !T_meas || !omega)) return S3A_EINVAL;
+  if (n_edges == 0) return S3A_OK;
+  DeviceGuard g(h->device);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  S3A_ORDERED(h, st);
+  S3A_TRY(launch_edges_from_alignment(n_edges, S, info, info_scale, T_meas, omega, edge_status, st));
+  return S3A_OK;
+}
+
 int s3a_pose_graph_solve(s3a_handle* h, int32_t n_nodes, int32_t n_edges, const int32_t* ij, const s3a_sim3* T_meas,
                          const double* omega, s3a_sim3* T, const s3a_pgo_params* params, s3a_pgo_report* report,
                          s3a_stream stream) {

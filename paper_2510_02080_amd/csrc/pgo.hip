@@ -1324,6 +1324,79 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
 
 }  // namespace
 
+// ------------------------------------------------------------------ edges from alignments
+
+// One lane per pair of an alignment batch: the registration result becomes a
+// pose-graph edge (Sec. III-C.2 feeding Sec. III-E). The alignment of source
+// points of submap j onto target points of submap i returns S = T_ij, and its
+// last Gauss-Newton matrix H for left perturbations S -> Exp(xi) S. A relative
+// pose T = Exp(xi) S has edge residual e = Log(S^-1 T) = Ad(S^-1) xi, so
+// 1/2 xi^T H xi = 1/2 e^T Ad(S)^T H Ad(S) e; with kappa = info_scale * n_valid,
+// Omega = kappa Ad(S)^T H Ad(S) (row-major, symmetric by construction: both
+// triangles are written from one product). A failed pair gives the identity
+// and Omega = 0, and its status is passed on.
+__global__ __launch_bounds__(64) void k_edges_from_alignment(int n, const s3a_sim3* S,
+                                                            const s3a_align_info* __restrict__ info,
+                                                            double info_scale, s3a_sim3* T_out,
+                                                            double* __restrict__ omega,
+                                                            int32_t* __restrict__ status) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  const s3a_align_info& in = info[e];
+  const int st = in.status;
+  s3a_sim3 T;
+  for (int k = 0; k < 16; ++k) (&T.R[0])[k] = 0.0;
+  double* Om = omega + 49 * (size_t)e;
+  if (st != S3A_PAIR_OK) {
+    T.R[0] = T.R[4] = T.R[8] = 1.0;
+    T.s = 1.0;
+    for (int k = 0; k < 49; ++k) Om[k] = 0.0;
+  } else {
+    Sim3d A;
+    for (int k = 0; k < 9; ++k) A.R[k] = S[e].R[k];
+    for (int k = 0; k < 3; ++k) A.t[k] = S[e].t[k];
+    A.s = S[e].s;
+    for (int k = 0; k < 9; ++k) T.R[k] = A.R[k];
+    for (int k = 0; k < 3; ++k) T.t[k] = A.t[k];
+    T.s = A.s;
+    double Ad[49], H[49], HA[49];
+    sim3_Ad(A, Ad);
+    // unpack the upper triangle (row-major) of H
+    int u = 0;
+    for (int r = 0; r < 7; ++r)
+      for (int c = r; c < 7; ++c) {
+        const double v = in.H[u++];
+        H[7 * r + c] = v;
+        H[7 * c + r] = v;
+      }
+    for (int r = 0; r < 7; ++r)
+      for (int c = 0; c < 7; ++c) {
+        double a = 0.0;
+        for (int k = 0; k < 7; ++k) a = fma(H[7 * r + k], Ad[7 * k + c], a);
+        HA[7 * r + c] = a;
+      }
+    const double kappa = info_scale * (double)in.n_valid;
+    for (int r = 0; r < 7; ++r)
+      for (int c = r; c < 7; ++c) {
+        double a = 0.0;
+        for (int k = 0; k < 7; ++k) a = fma(Ad[7 * k + r], HA[7 * k + c], a);
+        a *= kappa;
+        Om[7 * r + c] = a;
+        Om[7 * c + r] = a;
+      }
+  }
+  T_out[e] = T;
+  if (status) status[e] = st;
+}
+
+hipError_t launch_edges_from_alignment(int n, const s3a_sim3* S, const s3a_align_info* info, double info_scale,
+                                       s3a_sim3* T_out, double* omega, int32_t* status, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_edges_from_alignment, dim3((n + 63) / 64), dim3(64), 0, st, n, S, info, info_scale, T_out,
+                     omega, status);
+  return hipGetLastError();
+}
+
 void pgo_free(PgoWorkspace* ws) {
   if (!ws) return;
   if (ws->buf) (void)hipFree(ws->buf);
