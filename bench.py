@@ -9,9 +9,15 @@ storage. Only pairs whose pose matches the FP64 oracle within 1e-5 rad
 One timed step = one s3a_align_pairs call over the whole batch (inputs
 resident in HBM; a captured graph of one streaming launch and one FP64
 finalize launch per pass, replayed).
-Other legs on the same line: the same batch in BF16 storage, the plain
-per-pair path (one pair at a time, one launch per pass), the cost forward +
-adjoint, and the pose-graph solve, each with its own timing.
+Other legs on the same line, each with its own timing: the same batch in
+BF16 storage, the same batch as one persistent launch, the plain per-pair
+path (one pair at a time, one launch per pass), depth-map input, point
+correction, the cost forward + adjoint, the implicit derivative, and the
+loop-closure chain: 1199 edge pairs of 203,056 points aligned in one batched
+call, their results and Gauss-Newton matrices turned into pose-graph edges,
+and the 1000-node Huber-weighted pose-graph solve (Gauss-Newton and
+Levenberg-Marquardt). Every alignment result of every leg is checked against
+the FP64 oracle; a leg's points/s counts only pairs that pass.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--quick]
 """
@@ -38,6 +44,11 @@ POINTS_B_PER_PT = 12 + 12  # FP32 xyz in, FP32 world xyz out
 DEPTH_B_PER_PX = 12  # FP32 d_p, d_q, c per pixel
 IMPLICIT_B_PER_PT = 28 + 28 + 28  # Hessian pass reads, gradient pass reads and writes
 TOL = (1e-5, 1e-5, 1e-5)
+# Loop-closure edges: information = EDGE_INFO_SCALE * V * Ad(S)^T H Ad(S), with
+# 1/sigma^2 of the generator's point noise (sigma = 0.01 m); Huber threshold of
+# the whitened edge residual at the 95 % point of chi^2 with 7 degrees of freedom.
+EDGE_INFO_SCALE = 1.0 / 0.01 ** 2
+PGO_HUBER = 3.75
 
 # HBM traffic of the roofline kernel (k_pass, FP32, 256-pair batch) per pass
 # launch, averaged over the step's moments pass and 10 Gauss-Newton passes: the
@@ -95,14 +106,44 @@ def _verify_pair(args):
     return k, ok, err, len(p), dt
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _cores_available():
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def counted_points(ver, V_total):
+    """Points a leg's throughput counts: those of the pairs that passed the
+    oracle check (all points when checking is switched off)."""
+    if ver is None:
+        return V_total
+    if ver["checked"] == ver["n_pairs"]:
+        return ver["passed_points"]
+    # sampled check: scale by the passing fraction of the checked points
+    return int(V_total * ver["passed_points"] / max(ver["checked_points"], 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--quick", action="store_true", help="fewer pairs verified, no plain/config-1 leg")
+    ap.add_argument("--quick", action="store_true", help="shorter CPU baseline, no config-1 leg")
     ap.add_argument("--no-autotune", action="store_true")
-    ap.add_argument("--legs", default="bf16,depth,plain,adjoint,pgo,points", help="comma list of extra legs")
+    ap.add_argument("--legs", default="bf16,persistent,depth,plain,adjoint,pgo,points",
+                    help="comma list of extra legs")
     ap.add_argument("--verify", default="all", choices=["all", "sample", "none"])
     ap.add_argument("--workers", type=int, default=16)
     ap.add_argument("--tuning", default="", help="force the launch shape wg,items,occupancy (skips autotuning)")
@@ -115,6 +156,7 @@ def main():
         sys.exit(2)
     legs = set(x for x in args.legs.split(",") if x)
     log = lambda *a: print("[bench]", *a, file=sys.stderr, flush=True)
+    sample_every = {"all": 1, "sample": 8, "none": 1}[args.verify]
 
     # ---- synthetic inputs (host), before any GPU use
     t0 = time.perf_counter()
@@ -129,6 +171,10 @@ def main():
     if "depth" in legs:
         from synth import depthmaps
         _BATCHES["depth"] = depthmaps.config_depth()
+    if "pgo" in legs:
+        from synth import posegraph
+        E4, T4 = posegraph.config4_graph()
+        _BATCHES["cfg4"] = posegraph.edge_batch(T4, E4, workers=args.workers)
     log(f"generated inputs in {time.perf_counter() - t0:.1f}s: cfg2 {b2.n_pairs} pairs {b2.n_points} points")
     pool = mp.get_context("fork").Pool(args.workers) if args.verify != "none" else None
 
@@ -164,23 +210,28 @@ def main():
         h.set_timing(False)
         return ms / steps, n // steps
 
-    def verify(name, S, ib, sample_every=1):
+    def verify(name, S, ib):
+        """Every pair (every sample_every-th with --verify sample) against the
+        oracle, in the worker pool; wall_s is the pool's wall time."""
         if pool is None:
             return None
         b = _BATCHES[name]
         T = s3a.sim3_to_numpy(S)
         info = s3a.info_to_numpy(ib)
         ks = list(range(0, b.n_pairs, sample_every))
+        t = time.perf_counter()
         out = pool.map(_verify_pair, [(name, k, T[k], int(info["status"][k])) for k in ks], chunksize=1)
+        wall = time.perf_counter() - t
         ok = [o for o in out if o[1]]
         errs = np.array([o[2] for o in out if np.all(np.isfinite(o[2]))])
         V = info["n_valid"]
-        return dict(checked=len(out), passed=len(ok), passed_points=int(sum(V[o[0]] for o in ok)),
+        return dict(n_pairs=b.n_pairs, checked=len(out), passed=len(ok),
+                    passed_points=int(sum(V[o[0]] for o in ok)),
                     checked_points=int(sum(V[o[0]] for o in out)),
                     max_rot=float(errs[:, 0].max()) if len(errs) else None,
                     max_scale=float(errs[:, 1].max()) if len(errs) else None,
                     max_trans=float(errs[:, 2].max()) if len(errs) else None,
-                    oracle_cpu_s=float(sum(o[4] for o in out)),
+                    oracle_cpu_s=float(sum(o[4] for o in out)), wall_s=wall,
                     oracle_points=int(sum(o[3] for o in out)))
 
     # ---- headline: batched FP32, graph of per-pass launches
@@ -203,14 +254,8 @@ def main():
     info = s3a.info_to_numpy(ib)
     V_total = int(info["n_valid"].sum())
     log(f"batched fp32: {ms:.3f} ms/step, kernel {k_ms:.3f} ms ({k_n} launches), {V_total} valid points")
-    ver = verify("cfg2", S, ib, 1 if args.verify == "all" else 8)
-    if ver is not None and ver["checked"] == b2.n_pairs:
-        counted = ver["passed_points"]
-    elif ver is not None:
-        counted = V_total if ver["passed"] == ver["checked"] else int(V_total * ver["passed_points"] / max(ver["checked_points"], 1))
-    else:
-        counted = V_total
-    value = counted / (ms / 1e3)
+    ver = verify("cfg2", S, ib)
+    value = counted_points(ver, V_total) / (ms / 1e3)
     n_passes = 1 + b2.iters
     k_launch_ms = k_ms / n_passes  # timing mode: one event pair per pass launch
     bytes_per_launch = FP32_B_PER_PT * b2.n_points
@@ -219,6 +264,22 @@ def main():
     traffic = measured_traffic((used["wg"], used["items"], used["occupancy"]))
     res["batched_fp32"] = dict(ms_per_step=ms, kernel_ms=k_ms, points_per_s=value, verify=ver, tuning=tune)
     log(f"verify fp32: {ver}")
+
+    # ---- the same batch as one persistent launch (pass-major tickets), graph-captured
+    if "persistent" in legs:
+        Sp = torch.empty_like(S)
+        stepp = lambda: h.align_pairs(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT, out=Sp, info=False)
+        ms_p = timed(stepp, args.steps, args.warmup)
+        kp, _ = kernel_ms(stepp, args.steps)
+        Sp, ibp = h.align_pairs(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT)
+        torch.cuda.synchronize()
+        same = bool(torch.equal(Sp, S)) and bool(torch.equal(ibp, ib))
+        # bitwise equal to the checked graph-path result: the oracle verdict carries over
+        verp = dict(ver, bitwise_equal_to="batched_fp32") if (same and ver is not None) else verify("cfg2", Sp, ibp)
+        res["persistent_fp32"] = dict(ms_per_step=ms_p, kernel_ms=kp,
+                                      points_per_s=counted_points(verp, V_total) / (ms_p / 1e3),
+                                      vs_graph_path=ms / ms_p, bitwise_equal_graph_path=same, verify=verp)
+        log(f"persistent fp32: {ms_p:.3f} ms/step (kernel {kp:.3f} ms), graph path {ms:.3f} ms, bitwise equal {same}")
 
     # ---- BF16 storage
     if "bf16" in legs:
@@ -232,12 +293,14 @@ def main():
         k16, _ = kernel_ms(step16, args.steps)
         S16, ib16 = h.align_pairs(pm16, b16.tau, b16.delta, b16.iters)
         torch.cuda.synchronize()
-        ver16 = verify("cfg2-bf16", S16, ib16, 8 if args.verify != "none" else 1)
-        res["batched_bf16"] = dict(ms_per_step=ms16, kernel_ms=k16, points_per_s=V_total / (ms16 / 1e3),
-                                   pass_kernel_gbs=n_passes * BF16_B_PER_PT * b16.n_points / (k16 / 1e3) / 1e9,
-                                   roofline_frac=n_passes * BF16_B_PER_PT * b16.n_points / (k16 / 1e3) / 1e9 / HBM_PEAK_GBS,
-                                   verify=ver16)
-        log(f"batched bf16: {ms16:.3f} ms/step, kernel {k16:.3f} ms; verify {ver16}")
+        V16 = int(s3a.info_to_numpy(ib16)["n_valid"].sum())
+        ver16 = verify("cfg2-bf16", S16, ib16)
+        gbs16 = n_passes * BF16_B_PER_PT * b16.n_points / (k16 / 1e3) / 1e9
+        res["batched_bf16"] = dict(ms_per_step=ms16, kernel_ms=k16,
+                                   points_per_s=counted_points(ver16, V16) / (ms16 / 1e3),
+                                   pass_kernel_gbs=gbs16, roofline_frac=gbs16 / HBM_PEAK_GBS,
+                                   tuning=h.get_tuning(s3a.BF16, b16.n_points), verify=ver16)
+        log(f"batched bf16: {ms16:.3f} ms/step, kernel {k16:.3f} ms ({gbs16:.0f} GB/s); verify {ver16}")
         del pm16
 
     # ---- plain per-pair path (the speedup denominator)
@@ -257,11 +320,11 @@ def main():
             torch.cuda.synchronize()
             info1 = s3a.info_to_numpy(ib1)
             V1 = int(info1["n_valid"].sum())
-            ver1 = verify("cfg1", S1, ib1, 16 if args.verify != "none" else 1)
-            res["plain_fp32_cfg1"] = dict(ms_per_step=ms1, points_per_s=V1 / (ms1 / 1e3), n_pairs=b1.n_pairs,
-                                          valid_points=V1, verify=ver1,
-                                          batched_speedup=value / (V1 / (ms1 / 1e3)))
-            log(f"plain fp32 cfg1: {ms1:.2f} ms/step, {V1 / (ms1 / 1e3) / 1e9:.3f} Gpts/s; verify {ver1}")
+            ver1 = verify("cfg1", S1, ib1)
+            pps1 = counted_points(ver1, V1) / (ms1 / 1e3)
+            res["plain_fp32_cfg1"] = dict(ms_per_step=ms1, points_per_s=pps1, n_pairs=b1.n_pairs,
+                                          valid_points=V1, verify=ver1, batched_speedup=value / pps1)
+            log(f"plain fp32 cfg1: {ms1:.2f} ms/step, {pps1 / 1e9:.3f} Gpts/s; verify {ver1}")
             del pm1
 
     # ---- depth-map input: the same alignment with points unprojected inside the pass kernels
@@ -276,11 +339,12 @@ def main():
         torch.cuda.synchronize()
         infod = s3a.info_to_numpy(ibd)
         Vd = int(infod["n_valid"].sum())
-        verd = verify("depth", Sd, ibd, 16 if args.verify != "none" else 1)
+        verd = verify("depth", Sd, ibd)
         gbs_d = DEPTH_B_PER_PX * bd.n_points / (kd / kn / 1e3) / 1e9
-        res["depth_fp32"] = dict(ms_per_step=ms_d, points_per_s=Vd / (ms_d / 1e3), pixels=bd.n_points, valid_points=Vd,
+        ppsd = counted_points(verd, Vd) / (ms_d / 1e3)
+        res["depth_fp32"] = dict(ms_per_step=ms_d, points_per_s=ppsd, pixels=bd.n_points, valid_points=Vd,
                                  kernel_ms=kd, pass_gbs=gbs_d, pass_frac=gbs_d / HBM_PEAK_GBS, verify=verd)
-        log(f"depth fp32: {ms_d:.3f} ms/step, {Vd / (ms_d / 1e3) / 1e9:.2f} G valid pts/s over {bd.n_points} pixels, "
+        log(f"depth fp32: {ms_d:.3f} ms/step, {ppsd / 1e9:.2f} G valid pts/s over {bd.n_points} pixels, "
             f"pass {gbs_d:.0f} GB/s; verify {verd}")
         del dm
 
@@ -344,54 +408,98 @@ def main():
         log(f"implicit backward: {ms_i:.3f} ms (kernels {ki:.3f}, {res['implicit_fp32']['gbs']:.0f} GB/s)")
         del pm3
 
-    # ---- pose-graph solve: 1000 nodes, 999 sequential + 200 loop edges
+    # ---- loop closure: 1199 edge pairs aligned in one call -> edges -> 1000-node pose-graph solve
+    pgo_oracle = None
     if "pgo" in legs:
-        from synth.posegraph import config4_graph, noisy_measurements
-        E4, T4 = config4_graph()
-        meas = s3a.sim3_from_numpy(noisy_measurements(T4, E4, sigma=1e-3), dev)
-        Tn = torch.zeros((T4.shape[0], 16), dtype=torch.float64, device=dev)
-        h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True)  # symbolic analysis + warm-up
+        from oracle import metrics, pgo as pgo_oracle_mod, sim3 as sim3_oracle
+        b4 = _BATCHES["cfg4"]
+        n4 = int(T4.shape[0])
+        pm4 = s3a.Pointmaps.from_batch(b4, dev)
+        S4 = torch.empty((b4.n_pairs, 16), dtype=torch.float64, device=dev)
+        st4 = lambda: h.align_pairs(pm4, b4.tau, b4.delta, b4.iters, out=S4, info=False)
+        ms_a4 = timed(st4, 5, 1)
+        S4, ib4 = h.align_pairs(pm4, b4.tau, b4.delta, b4.iters)
+        torch.cuda.synchronize()
+        V4 = int(s3a.info_to_numpy(ib4)["n_valid"].sum())
+        edge_step = lambda: h.edges_from_alignment(S4, ib4, EDGE_INFO_SCALE)
+        ms_e4 = timed(edge_step, args.steps, args.warmup)
+        Tm, Om, est = h.edges_from_alignment(S4, ib4, EDGE_INFO_SCALE)
+        Tn = torch.zeros((n4, 16), dtype=torch.float64, device=dev)
+        solve = lambda lm=False, iters=20: h.pose_graph_solve(E4, Tm, Tn, omega=Om, iters=iters, huber_delta=PGO_HUBER,
+                                                              init_chain=True, lm=lm)
+        solve()  # symbolic analysis + warm-up
         torch.cuda.synchronize()
         reps = 3
         t = time.perf_counter()
         for _ in range(reps):
-            _, rep = h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True)
+            _, rep = solve()
         ms_pgo = (time.perf_counter() - t) / reps * 1e3
-        res["pgo_fp64"] = dict(ms_per_solve=ms_pgo, iters=20, nodes=int(T4.shape[0]), edges=int(len(E4)),
-                               chi2_first=rep.chi2[0], chi2_final=rep.final_chi2, status=rep.status,
-                               factor_blocks=int(rep.factor_nnz_blocks))
-        log(f"pgo: {ms_pgo:.2f} ms per 20-iteration solve, chi2 {rep.chi2[0]:.4g} -> {rep.final_chi2:.4g}")
-        # Levenberg-Marquardt, the optimiser the paper names: up to 20 kept steps
-        h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True, lm=True)
+        Tg = s3a.sim3_to_numpy(Tn)
+        solve(lm=True)
         torch.cuda.synchronize()
         t = time.perf_counter()
         for _ in range(reps):
-            _, rl = h.pose_graph_solve(E4, meas, Tn, iters=20, init_chain=True, lm=True)
+            _, rl = solve(lm=True)
         ms_lm = (time.perf_counter() - t) / reps * 1e3
-        res["pgo_lm_fp64"] = dict(ms_per_solve=ms_lm, kept_steps=rl.iters, rejected=rl.rejected, stalled=rl.stalled,
-                                  chi2_first=rl.chi2[0], chi2_final=rl.final_chi2, lambda_final=rl.lambda_final)
-        log(f"pgo LM: {ms_lm:.2f} ms ({rl.iters} kept, {rl.rejected} rejected), chi2 {rl.chi2[0]:.4g} -> "
-            f"{rl.final_chi2:.4g}")
+        Tlm = s3a.sim3_to_numpy(Tn)
+        # one Gauss-Newton iteration from the chained start, GPU vs the FP64 dense oracle on the same edges
+        _, r1 = solve(iters=1)
+        T1 = s3a.sim3_to_numpy(Tn)
+        Sg4 = s3a.sim3_to_numpy(Tm)
+        Omg = Om.cpu().numpy().reshape(-1, 7, 7)
+        ver4 = verify("cfg4", S4, ib4)
+        t = time.perf_counter()
+        ref1 = pgo_oracle_mod.pgo_solve(n4, E4, Sg4, Omg, None, 1, huber_delta=PGO_HUBER)
+        pgo_iter_s = time.perf_counter() - t
+        it_err = max(max(metrics.pose_errors(sim3_oracle.to_srt(a), sim3_oracle.to_srt(c)))
+                     for a, c in zip(T1, ref1["T"]))
+        ate = lambda T: float(np.sqrt(np.mean([np.sum((T[k][:3, 3] - T4[k][:3, 3]) ** 2) for k in range(n4)])))
+        T0 = pgo_oracle_mod.chain_init(n4, E4, Sg4)
+        res["loop_closure_fp64"] = dict(
+            edges=int(len(E4)), nodes=n4, edge_points=b4.n_points, edge_valid_points=V4,
+            align_ms=ms_a4, align_points_per_s=counted_points(ver4, V4) / (ms_a4 / 1e3), align_verify=ver4,
+            edges_from_alignment_ms=ms_e4, edge_status_ok=int((est.cpu().numpy() == 0).sum()),
+            gn_ms_per_solve=ms_pgo, gn_iters=20, chi2_first=rep.chi2[0], chi2_final=rep.final_chi2,
+            status=rep.status, factor_blocks=int(rep.factor_nnz_blocks),
+            lm_ms_per_solve=ms_lm, lm_kept_steps=rl.iters, lm_rejected=rl.rejected, lm_chi2_final=rl.final_chi2,
+            ate_chained_m=ate(T0), ate_gn_m=ate(Tg), ate_lm_m=ate(Tlm),
+            first_iterate_vs_oracle=it_err, first_iterate_chi2=r1.chi2[0], huber_delta=PGO_HUBER,
+            info_scale=EDGE_INFO_SCALE)
+        pgo_oracle = dict(s_per_gn_iteration=pgo_iter_s, s_per_20_iterations_est=20 * pgo_iter_s,
+                          sample="one dense FP64 Gauss-Newton iteration of the 1000-node, 1199-edge graph")
+        log(f"loop closure: align {b4.n_pairs} pairs {ms_a4:.2f} ms, edges {ms_e4:.3f} ms, GN {ms_pgo:.2f} ms, "
+            f"LM {ms_lm:.2f} ms ({rl.iters} kept), ATE chained {ate(T0):.4f} -> GN {ate(Tg):.4f} m; first iterate vs "
+            f"oracle {it_err:.3g} (oracle {pgo_iter_s:.1f} s/iter); verify {ver4}")
+        del pm4
 
-    # ---- CPU baseline: the oracle as it stands, one core, bounded sample
-    cpu = None
-    if pool is not None or True:
-        from threadpoolctl import threadpool_limits
-        from oracle import irls
-        pts, secs, ks = 0, 0.0, []
-        with threadpool_limits(1):
-            for k in np.argsort(b2.counts())[b2.n_pairs // 2:]:  # median-and-up sizes, one at a time
-                p, q, c = b2.decoded_pair(int(k))
-                t = time.perf_counter()
-                irls.irls_align(p, q, c, b2.tau, b2.delta, b2.iters)
-                secs += time.perf_counter() - t
-                pts += len(p)
-                ks.append(int(k))
-                if secs > (8.0 if args.quick else 15.0):
-                    break
-        cpu = dict(value=pts / secs, unit="aligned points/s", cores=1, kind="oracle",
-                   sample=f"{len(ks)} pairs of the batched workload ({pts} points), FP64 oracle, 1 thread")
-        log(f"cpu baseline {cpu}")
+    # ---- CPU baseline: the oracle as it stands, one core, bounded sample; all-core figures from the checks
+    from threadpoolctl import threadpool_limits
+    from oracle import irls
+    pts, secs, ks = 0, 0.0, []
+    with threadpool_limits(1):
+        for k in np.argsort(b2.counts())[b2.n_pairs // 2:]:  # median-and-up sizes, one at a time
+            p, q, c = b2.decoded_pair(int(k))
+            t = time.perf_counter()
+            irls.irls_align(p, q, c, b2.tau, b2.delta, b2.iters)
+            secs += time.perf_counter() - t
+            pts += len(p)
+            ks.append(int(k))
+            if secs > (8.0 if args.quick else 15.0):
+                break
+    cpu = dict(value=pts / secs, unit="aligned points/s", cores=1, kind="oracle",
+               sample=f"{len(ks)} pairs of the batched workload ({pts} points), FP64 oracle, 1 thread",
+               cpu_model=_cpu_model(), cores_available=_cores_available())
+    if ver is not None and ver["checked"] == b2.n_pairs:
+        cpu["all_cores"] = dict(value=ver["oracle_points"] / ver["wall_s"], cores=args.workers,
+                                sample=f"all {b2.n_pairs} pairs of the batched workload, one pair per process")
+    v1 = res.get("plain_fp32_cfg1", {}).get("verify")
+    if v1 is not None and v1["checked"] == v1["n_pairs"]:
+        cpu["cfg1_all_cores"] = dict(value=v1["oracle_points"] / v1["wall_s"], cores=args.workers,
+                                     one_thread=v1["oracle_points"] / v1["oracle_cpu_s"],
+                                     sample=f"all {v1['n_pairs']} consecutive pairs of 203,056 points")
+    if pgo_oracle is not None:
+        cpu["pgo_oracle"] = pgo_oracle
+    log(f"cpu baseline {cpu}")
 
     if pool is not None:
         pool.close()

@@ -85,8 +85,10 @@ _EDGE_JOB = {}
 
 def _fill_edge(k):
     """Generate edge pair k into the shared planes (runs in a forked worker)."""
+    from threadpoolctl import threadpool_limits
     job = _EDGE_JOB
-    p, q, c, _ = edge_pair(job["T"], job["edges"][k], k, job["H"], job["W"], job["seed"])
+    with threadpool_limits(1):  # one BLAS thread per worker process
+        p, q, c, _ = edge_pair(job["T"], job["edges"][k], k, job["H"], job["W"], job["seed"])
     a = k * job["H"] * job["W"]
     b = a + len(p)
     pl = job["planes"]
