@@ -47,6 +47,8 @@
  *     delta <= 0 or NaN, tau < 0 or NaN, iters < 0, misaligned plane).
  *     S3A_EHIP: a HIP runtime error (code kept, s3a_last_hip_error).
  *     S3A_ENOMEM: workspace allocation failed.
+ *     S3A_ELIMIT: the batch is larger than s3a_align_pairs_noalloc's fixed
+ *     scratch holds.
  *   - Problems of one pair do not fail the call: they are reported in that
  *     pair's status (S3A_PAIR_*), and the pair's outputs are the identity with
  *     cost NaN. Other pairs are unaffected, with one exception: invalid
@@ -77,7 +79,7 @@ typedef struct {
 
 enum { S3A_F32 = 0, S3A_BF16 = 1 };
 
-enum { S3A_OK = 0, S3A_EINVAL = -1, S3A_EHIP = -2, S3A_ENOMEM = -3 };
+enum { S3A_OK = 0, S3A_EINVAL = -1, S3A_EHIP = -2, S3A_ENOMEM = -3, S3A_ELIMIT = -4 };
 
 /* Per-pair status. */
 enum {
@@ -156,6 +158,37 @@ int s3a_destroy(s3a_handle* h);
  */
 int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* desc, const s3a_sim3* init,
                     s3a_sim3* S_out, s3a_align_info* info, s3a_stream stream);
+
+/*
+ * Allocation-free variant of s3a_align_pairs, for callers that cannot
+ * allocate device memory: code being captured into a HIP graph, tight serving
+ * loops, hosts that forbid allocation after start-up. It takes no handle,
+ * allocates nothing and makes no host-device copy: it only enqueues kernels.
+ *   - It runs on the calling thread's current device; `stream` must belong to
+ *     that device. Arguments, outputs and per-pair statuses are those of
+ *     s3a_align_pairs (batched path).
+ *   - Every temporary lives in one fixed scratch array of
+ *     S3A_NOALLOC_SCRATCH_BYTES per device, held by the library until the
+ *     process ends. Limits: n_pairs <= S3A_NOALLOC_MAX_PAIRS, and the batch's
+ *     tile bound n_points / 8192 + 2 n_pairs + 1 <= S3A_NOALLOC_MAX_TILES
+ *     (about 260 million points); beyond them the call returns S3A_ELIMIT and
+ *     enqueues nothing.
+ *   - Launch shape fixed at tiles of 8192 elements, one workgroup per tile
+ *     (FP32: 512 threads x 4 vectors; BF16: 256 x 4). The results equal, bit
+ *     for bit, s3a_align_pairs' with that launch shape.
+ *   - Flags: S3A_FLAG_FINAL_COST; S3A_FLAG_NO_GRAPH is accepted and changes
+ *     nothing; S3A_FLAG_PLAIN and S3A_FLAG_PERSISTENT return S3A_EINVAL.
+ *   - All calls on one device share that device's scratch array, which keeps
+ *     the last call's contents (each call writes every word it reads before
+ *     reading it). Calls that can overlap on one device (two streams, or two
+ *     threads) race on it and must be serialised by the caller. Calls through
+ *     a handle do not use it.
+ */
+#define S3A_NOALLOC_MAX_PAIRS 4096
+#define S3A_NOALLOC_MAX_TILES 32768
+#define S3A_NOALLOC_SCRATCH_BYTES (12u << 20)
+int s3a_align_pairs_noalloc(const s3a_align_desc* desc, const s3a_sim3* init, s3a_sim3* S_out,
+                            s3a_align_info* info, s3a_stream stream);
 
 /*
  * Depth-map input (Sec. III-C.1: a submap is its keyframes' predicted depth

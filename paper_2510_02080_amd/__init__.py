@@ -10,7 +10,8 @@ fallback.
 
 from .binding import (BF16, F32, FLAG_FINAL_COST, FLAG_PERSISTENT, FLAG_NO_GRAPH, FLAG_PLAIN, INFO_DTYPE,
                       PAIR_ABORTED, PAIR_BADRANGE, PAIR_DEGENERATE, PAIR_EMPTY, PAIR_NONFINITE, PAIR_OK, Handle, Pointmaps,
-                      S3AError, DepthPointmaps, info_to_numpy, load_library, sim3_from_numpy, sim3_to_numpy)
+                      S3AError, DepthPointmaps, align_pairs_noalloc, info_to_numpy, load_library, sim3_from_numpy,
+                      sim3_to_numpy)
 from .autograd import AlignCost, AlignSolve, align_cost as align_cost_autograd, align_solve
 
 _handles = {}

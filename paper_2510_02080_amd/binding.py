@@ -12,7 +12,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libs3a.so")
 
 F32, BF16 = 0, 1
-OK, EINVAL, EHIP, ENOMEM = 0, -1, -2, -3
+OK, EINVAL, EHIP, ENOMEM, ELIMIT = 0, -1, -2, -3, -4
+NOALLOC_MAX_PAIRS, NOALLOC_MAX_TILES, NOALLOC_TILE = 4096, 32768, 8192
 PAIR_OK, PAIR_EMPTY, PAIR_DEGENERATE, PAIR_NONFINITE, PAIR_BADRANGE, PAIR_ABORTED = range(6)
 FLAG_PLAIN, FLAG_FINAL_COST, FLAG_NO_GRAPH, FLAG_PERSISTENT = 0x1, 0x2, 0x4, 0x8
 PGO_INIT_CHAIN, PGO_LM = 0x1, 0x2
@@ -87,6 +88,7 @@ _EXPORTS = {
                                              c_void_p]),
     "s3a_edges_from_alignment": (ctypes.c_int, [c_void_p, ctypes.c_int32, c_void_p, c_void_p, ctypes.c_double,
                                                 c_void_p, c_void_p, c_void_p, c_void_p]),
+    "s3a_align_pairs_noalloc": (ctypes.c_int, [ctypes.POINTER(AlignDesc), c_void_p, c_void_p, c_void_p, c_void_p]),
     "s3a_strerror": (ctypes.c_char_p, [ctypes.c_int]),
     "s3a_last_hip_error": (ctypes.c_int, [c_void_p]),
     "s3a_version": (ctypes.c_int, []),
@@ -416,6 +418,24 @@ class Handle:
         t = Tuning()
         _check(self.lib.s3a_get_tuning(self.h, dtype, n_points, ctypes.byref(t)))
         return dict(wg=t.wg, items=t.items, occupancy=t.occupancy, window=t.window)
+
+
+def align_pairs_noalloc(pm, tau, delta=0.05, iters=10, init=None, flags=0, out=None, info=None):
+    """s3a_align_pairs_noalloc: the batched alignment with no handle and no
+    device allocation inside the library, on pm's device (made current) and
+    torch's current stream there. out (n, 16) float64 and info (n, info
+    bytes) uint8 may be given to keep the call free of torch allocations too
+    (info=False: no diagnostics). Returns (S, info buffer or None)."""
+    lib = load_library()
+    n = pm.n_pairs
+    S = out if out is not None else torch.empty((n, SIM3_DOUBLES), dtype=torch.float64, device=pm.device)
+    if info is None:
+        info = torch.empty((n, INFO_DTYPE.itemsize), dtype=torch.uint8, device=pm.device)
+    ib = info if info is not False else None
+    d = pm.desc(tau, delta, iters, flags)
+    with torch.cuda.device(pm.device):
+        _check(lib.s3a_align_pairs_noalloc(ctypes.byref(d), _ptr(init), _ptr(S), _ptr(ib), _stream(pm.device)))
+    return S, ib
 
 
 def info_to_numpy(ib):

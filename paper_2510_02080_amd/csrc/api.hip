@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <mutex>
 #include <vector>
 
 #include "align_launch.h"
@@ -339,6 +340,7 @@ const char* s3a_strerror(int code) {
     case S3A_EINVAL: return "invalid argument";
     case S3A_EHIP: return "HIP runtime error";
     case S3A_ENOMEM: return "out of device memory";
+    case S3A_ELIMIT: return "batch exceeds the fixed scratch of the allocation-free entry point";
     default: return "unknown error";
   }
 }
@@ -502,6 +504,128 @@ int align_run(s3a_handle* h, const s3a_align_desc* d, const s3a_depth_pair* dept
 }
 
 }  // namespace
+
+// ------------------------------------------------------------------ allocation-free alignment
+//
+// s3a_align_pairs_noalloc runs the batched sequence (schedule, then per pass
+// one streaming launch and one finalize launch) with every temporary in one
+// fixed device array per device, laid out below. Its launch shape is fixed,
+// so no autotuning state is needed either.
+
+namespace {
+
+constexpr size_t align_c(size_t x) { return (x + 255) & ~size_t(255); }
+
+constexpr int NA_PAIRS = S3A_NOALLOC_MAX_PAIRS;
+constexpr int64_t NA_TILES = S3A_NOALLOC_MAX_TILES;
+constexpr size_t NA_O_DESC = 0;
+constexpr size_t NA_O_TOTAL = align_c(NA_O_DESC + sizeof(CallDesc));
+constexpr size_t NA_O_SCHED = align_c(NA_O_TOTAL + sizeof(int32_t) * 64);
+constexpr size_t NA_O_PARAMS = align_c(NA_O_SCHED + sizeof(PairSched) * NA_PAIRS);
+constexpr size_t NA_O_STATE = align_c(NA_O_PARAMS + sizeof(PointParams) * NA_PAIRS);
+constexpr size_t NA_O_TILES = align_c(NA_O_STATE + sizeof(PairState) * NA_PAIRS);
+constexpr size_t NA_O_PART = align_c(NA_O_TILES + sizeof(TileDesc) * NA_TILES);
+constexpr size_t NA_BYTES = align_c(NA_O_PART + sizeof(double) * NSTAT * NA_TILES);
+static_assert(NA_BYTES <= S3A_NOALLOC_SCRATCH_BYTES, "scratch layout exceeds its stated size");
+
+}  // namespace
+
+// The scratch array: one copy per device, held until the process ends. Host
+// code never names it in a launch or copy; it uses the device address that
+// hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) unsigned char scratch[S3A_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NA_MAX_DEVICES = 64;
+std::mutex na_mutex;
+unsigned char* na_ptr[NA_MAX_DEVICES] = {};
+
+// Device address of the current device's scratch array (looked up once per device).
+int noalloc_scratch(unsigned char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return S3A_EHIP;
+  if (dev >= NA_MAX_DEVICES) return S3A_EINVAL;
+  std::lock_guard<std::mutex> lock(na_mutex);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return S3A_EHIP;
+    na_ptr[dev] = static_cast<unsigned char*>(p);
+  }
+  *out = na_ptr[dev];
+  return S3A_OK;
+}
+
+// The call's descriptor reaches the device as a kernel argument (no host copy).
+__global__ void k_store_desc(CallDesc c, CallDesc* dst) {
+  if (threadIdx.x == 0) *dst = c;
+}
+
+// Fixed launch shapes: 8192-element tiles, one workgroup per tile.
+LaunchCfg noalloc_cfg(int dtype) {
+  LaunchCfg c;
+  c.wg = dtype == S3A_F32 ? 512 : 256;
+  c.items = 4;
+  c.occupancy = 0;
+  c.window = 0;
+  return c;
+}
+
+}  // namespace
+
+extern "C" {
+
+int s3a_align_pairs_noalloc(const s3a_align_desc* d, const s3a_sim3* init, s3a_sim3* S_out,
+                            s3a_align_info* info, s3a_stream stream) {
+  int rc = check_desc(d);
+  if (rc) return rc;
+  if (d->flags & (S3A_FLAG_PLAIN | S3A_FLAG_PERSISTENT)) return S3A_EINVAL;
+  if (d->n_pairs > 0 && !S_out) return S3A_EINVAL;
+  if (d->n_pairs == 0) return S3A_OK;
+  const LaunchCfg lc = noalloc_cfg(d->dtype);
+  const Shape sh = make_shape(d, lc);
+  const int64_t mt = max_tiles(sh.n_points, sh.n_pairs, sh.tile_elems);
+  if (d->n_pairs > NA_PAIRS || mt > NA_TILES) return S3A_ELIMIT;
+  unsigned char* base = nullptr;
+  rc = noalloc_scratch(&base);
+  if (rc) return rc;
+  Work w{};
+  w.tiles = reinterpret_cast<TileDesc*>(base + NA_O_TILES);
+  w.partials = reinterpret_cast<double*>(base + NA_O_PART);
+  w.sched = reinterpret_cast<PairSched*>(base + NA_O_SCHED);
+  w.params = reinterpret_cast<PointParams*>(base + NA_O_PARAMS);
+  w.state = reinterpret_cast<PairState*>(base + NA_O_STATE);
+  w.total_tiles = reinterpret_cast<int32_t*>(base + NA_O_TOTAL);
+  w.counters = nullptr;  // persistent launch only
+  w.flags = nullptr;
+  w.scan_tmp = nullptr;
+  w.dpairs = nullptr;    // depth input only
+  CallDesc c = make_call(d);
+  c.init = init;
+  c.S_out = S_out;
+  c.info = info;
+  CallDesc* dcd = reinterpret_cast<CallDesc*>(base + NA_O_DESC);
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_store_desc, dim3(1), dim3(64), 0, st, c, dcd);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(nullptr, e);
+  // every scratch word a kernel reads is written earlier in the same call:
+  // the schedule and tile table by k_sched/k_sched_fill, each tile's partials
+  // by its pass, each pair's state and parameters by the moments finalize
+  e = launch_sched(sh, dcd, w, st);
+  if (e != hipSuccess) return hip_fail(nullptr, e);
+  const int grid = (int)std::max<int64_t>(mt, 1);
+  const int npass = 1 + sh.K + ((sh.flags & S3A_FLAG_FINAL_COST) ? 1 : 0);
+  for (int pass = 0; pass < npass; ++pass) {
+    e = launch_pass(d->dtype, pass == 0 ? MODE_MOMENTS : MODE_GN, lc, sh, dcd, w, 0, -1, grid, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e);
+    e = launch_finalize(pass == 0 ? 0 : (pass <= sh.K ? 1 : 2), sh, dcd, w, pass, 0, sh.n_pairs, st);
+    if (e != hipSuccess) return hip_fail(nullptr, e);
+  }
+  return S3A_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 

@@ -90,3 +90,31 @@ def test_host_argument_checks(lib):
     assert L.s3a_align_pairs_implicit_backward(None, ctypes.byref(d), None, None, 0, *([None] * 9), None) == b.EINVAL
     assert L.s3a_transform_points(None, 0, 0, 0, None, *([None] * 8), None) == b.EINVAL
     assert L.s3a_correct_points(None, 0, None, None, 0, None, None, None, 0, None, None, None, None, None) == b.EINVAL
+
+
+def test_noalloc_rejects_before_touching_a_device(lib):
+    """The allocation-free entry point checks its arguments and its fixed
+    limits on the host: nothing reaches a device (there is none here)."""
+    from paper_2510_02080_amd import binding as b
+    L = b.load_library(LIB)
+    assert L.s3a_align_pairs_noalloc(None, None, None, None, None) == b.EINVAL
+    fake = 4096  # never dereferenced on the host
+    d = b.AlignDesc()
+    d.dtype = b.F32
+    d.n_pairs = b.NOALLOC_MAX_PAIRS + 1
+    d.n_points = 0
+    d.offsets = fake
+    d.conf_threshold = 1.5
+    d.irls_iters = 10
+    d.huber_delta = 0.05
+    assert L.s3a_align_pairs_noalloc(ctypes.byref(d), None, None, None, None) == b.EINVAL  # no S_out
+    assert L.s3a_align_pairs_noalloc(ctypes.byref(d), None, fake, None, None) == b.ELIMIT
+    # too many points for the tile table: n / 8192 + 2 n_pairs + 1 > max tiles
+    d.n_pairs = 1
+    d.n_points = (b.NOALLOC_MAX_TILES - 2) * b.NOALLOC_TILE
+    for nm in ("px", "py", "pz", "qx", "qy", "qz", "conf"):
+        setattr(d, nm, fake)
+    assert L.s3a_align_pairs_noalloc(ctypes.byref(d), None, fake, None, None) == b.ELIMIT
+    d.flags = 0x1  # S3A_FLAG_PLAIN
+    assert L.s3a_align_pairs_noalloc(ctypes.byref(d), None, fake, None, None) == b.EINVAL
+    assert L.s3a_strerror(b.ELIMIT).startswith(b"batch exceeds")
