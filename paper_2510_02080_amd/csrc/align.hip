@@ -170,20 +170,24 @@ hipError_t launch_pass(int dtype, int mode, const LaunchCfg& lc, const Shape& sh
   if (dtype == DT_DEPTH_F32) {
     if (mode == MODE_MOMENTS) return launch_pass_t<DT_DEPTH_F32, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_GN) return launch_pass_t<DT_DEPTH_F32, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN_NC) return launch_pass_t<DT_DEPTH_F32, MODE_GN_NC>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     return hipErrorInvalidValue;
   }
   if (dtype == DT_DEPTH_BF16) {
     if (mode == MODE_MOMENTS) return launch_pass_t<DT_DEPTH_BF16, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_GN) return launch_pass_t<DT_DEPTH_BF16, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN_NC) return launch_pass_t<DT_DEPTH_BF16, MODE_GN_NC>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     return hipErrorInvalidValue;
   }
   if (dtype == S3A_F32) {
     if (mode == MODE_MOMENTS) return launch_pass_t<S3A_F32, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_GN) return launch_pass_t<S3A_F32, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN_NC) return launch_pass_t<S3A_F32, MODE_GN_NC>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_COST) return launch_pass_t<S3A_F32, MODE_COST>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
   } else {
     if (mode == MODE_MOMENTS) return launch_pass_t<S3A_BF16, MODE_MOMENTS>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_GN) return launch_pass_t<S3A_BF16, MODE_GN>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
+    if (mode == MODE_GN_NC) return launch_pass_t<S3A_BF16, MODE_GN_NC>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
     if (mode == MODE_COST) return launch_pass_t<S3A_BF16, MODE_COST>(lc, sh, cd, w, tile_lo, tile_hi, grid, st);
   }
   return hipErrorInvalidValue;

@@ -56,24 +56,49 @@ struct SrcCtx<DT_DEPTH_F32> : DepthCtx {};
 template <>
 struct SrcCtx<DT_DEPTH_BF16> : DepthCtx {};
 
+// Stored xyz planes are read in two steps: fetch() issues one 16-byte vector
+// per plane into raw registers (so a tile body can have the next vectors in
+// flight while it works on the current ones), unpack() turns them into floats.
+// A vector that runs past the end of the planes is gathered element by element
+// (zeros past the end) into the same raw form.
+typedef s3a_u4 RawVec[7];
+
 template <>
 struct Planes<S3A_F32> {
   static constexpr int VEC = 4;
-  __device__ static inline void load(const SrcCtx<S3A_F32>& src, int64_t g0, int64_t n, float (&v)[7][4]) {
+  __device__ static inline void fetch(const SrcCtx<S3A_F32>& src, int64_t g0, int64_t n, RawVec& r) {
     const void* const* pl = src.pl;
     if (g0 + 4 <= n) {
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        const s3a_f4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_f4*)(static_cast<const float*>(pl[j]) + g0));
-        v[j][0] = x.x; v[j][1] = x.y; v[j][2] = x.z; v[j][3] = x.w;
-      }
+      for (int j = 0; j < 7; ++j)
+        r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint32_t*>(pl[j]) + g0));
     } else {
 #pragma unroll
       for (int j = 0; j < 7; ++j)
 #pragma unroll
         for (int e = 0; e < 4; ++e)
-          v[j][e] = (g0 + e < n) ? static_cast<const float*>(pl[j])[g0 + e] : 0.0f;
+          r[j][e] = (g0 + e < n) ? static_cast<const uint32_t*>(pl[j])[g0 + e] : 0u;
     }
+  }
+  __device__ static inline void unpack(const RawVec& r, float (&v)[7][4]) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) v[j][e] = __uint_as_float(r[j][e]);
+  }
+  __device__ static inline void load(const SrcCtx<S3A_F32>& src, int64_t g0, int64_t n, float (&v)[7][4]) {
+    RawVec r;
+    fetch(src, g0, n, r);
+    unpack(r, v);
+  }
+  // element e of plane j of a raw vector; its finiteness; zeroing it
+  __device__ static inline float elem(const RawVec& r, int j, int e) { return __uint_as_float(r[j][e]); }
+  __device__ static inline bool elem_finite(const RawVec& r, int j, int e) {
+    return (r[j][e] & 0x7f800000u) != 0x7f800000u;
+  }
+  __device__ static inline void keep_elem(RawVec& r, int e, bool keep) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j) r[j][e] = keep ? r[j][e] : 0u;
   }
 };
 
@@ -82,24 +107,87 @@ struct Planes<S3A_BF16> {
   static constexpr int VEC = 8;
   __device__ static inline float lo(uint32_t u) { return __uint_as_float(u << 16); }
   __device__ static inline float hi(uint32_t u) { return __uint_as_float(u & 0xffff0000u); }
-  __device__ static inline void load(const SrcCtx<S3A_BF16>& src, int64_t g0, int64_t n, float (&v)[7][8]) {
+  __device__ static inline void fetch(const SrcCtx<S3A_BF16>& src, int64_t g0, int64_t n, RawVec& r) {
     const void* const* pl = src.pl;
     if (g0 + 8 <= n) {
 #pragma unroll
-      for (int j = 0; j < 7; ++j) {
-        const s3a_u4 x = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(pl[j]) + g0));
-        v[j][0] = lo(x.x); v[j][1] = hi(x.x); v[j][2] = lo(x.y); v[j][3] = hi(x.y);
-        v[j][4] = lo(x.z); v[j][5] = hi(x.z); v[j][6] = lo(x.w); v[j][7] = hi(x.w);
-      }
+      for (int j = 0; j < 7; ++j)
+        r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(pl[j]) + g0));
     } else {
 #pragma unroll
       for (int j = 0; j < 7; ++j)
 #pragma unroll
-        for (int e = 0; e < 8; ++e)
-          v[j][e] = (g0 + e < n) ? lo(static_cast<const uint16_t*>(pl[j])[g0 + e]) : 0.0f;
+        for (int i = 0; i < 4; ++i) {
+          const uint16_t* h = static_cast<const uint16_t*>(pl[j]);
+          const uint32_t a = (g0 + 2 * i < n) ? h[g0 + 2 * i] : 0u;
+          const uint32_t b = (g0 + 2 * i + 1 < n) ? h[g0 + 2 * i + 1] : 0u;
+          r[j][i] = a | (b << 16);
+        }
     }
   }
+  __device__ static inline void unpack(const RawVec& r, float (&v)[7][8]) {
+#pragma unroll
+    for (int j = 0; j < 7; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        v[j][2 * i] = lo(r[j][i]);
+        v[j][2 * i + 1] = hi(r[j][i]);
+      }
+  }
+  __device__ static inline void load(const SrcCtx<S3A_BF16>& src, int64_t g0, int64_t n, float (&v)[7][8]) {
+    RawVec r;
+    fetch(src, g0, n, r);
+    unpack(r, v);
+  }
+  // element e (half e % 2 of word e / 2) of plane j of a raw vector; its finiteness; zeroing it
+  __device__ static inline float elem(const RawVec& r, int j, int e) {
+    return (e & 1) ? hi(r[j][e >> 1]) : lo(r[j][e >> 1]);
+  }
+  __device__ static inline bool elem_finite(const RawVec& r, int j, int e) {
+    const uint32_t m = (e & 1) ? 0x7f800000u : 0x00007f80u;
+    return (r[j][e >> 1] & m) != m;
+  }
+  __device__ static inline void keep_elem(RawVec& r, int e, bool keep) {
+    const uint32_t m = (e & 1) ? 0x0000ffffu : 0xffff0000u;  // the other half
+#pragma unroll
+    for (int j = 0; j < 7; ++j) r[j][e >> 1] = keep ? r[j][e >> 1] : (r[j][e >> 1] & m);
+  }
 };
+
+// Walk the lane's vectors of a tile: item it = 0 .. ITEMS-1 starts at element
+// rel0 = (it * WG + lane) * VEC after the tile's first. Two raw buffers
+// alternate: the next item's loads are issued before the current item is
+// worked on, so every wavefront keeps loads in flight while it computes.
+// fetch(rel, raw) issues the loads of the vector at rel; body(raw, rel0)
+// consumes one. ITEMS is even. A lane runs the items with rel0 < end_rel; with
+// UNIFORM, every lane runs every item that starts before end_rel for some lane
+// (end_rel is the same for the whole workgroup), so that the body may use
+// cross-lane operations, and masks elements at or past end_rel itself (the
+// fetch bounds-checks against the planes' end).
+template <int WG, int ITEMS, int VEC, typename Raw, bool UNIFORM = false, typename Fetch, typename Body>
+__device__ inline void pipelined_items(int end_rel, Fetch&& fetch, Body&& body) {
+  static_assert(ITEMS % 2 == 0, "items per lane must be even");
+  constexpr int STRIDE = WG * VEC;
+  Raw A, B;
+  const int first = (int)threadIdx.x * VEC;
+  if (UNIFORM ? end_rel <= 0 : first >= end_rel) return;
+  fetch(first, A);
+#pragma unroll 1
+  for (int it = 0; it < ITEMS; it += 2) {
+    const int base = it * STRIDE;
+    const int r0 = first + base;
+    const int r1 = r0 + STRIDE;
+    const bool more1 = UNIFORM ? base + STRIDE < end_rel : r1 < end_rel;
+    if (more1) fetch(r1, B);
+    body(A, r0);
+    if (!more1) break;
+    const int r2 = r1 + STRIDE;
+    const bool more2 = it + 2 < ITEMS && (UNIFORM ? base + 2 * STRIDE < end_rel : r2 < end_rel);
+    if (more2) fetch(r2, A);
+    body(B, r1);
+    if (!more2) break;
+  }
+}
 
 // Gradients are written once and not read back by the library: streaming
 // (non-temporal) global stores.
@@ -233,6 +321,47 @@ struct DepthPlanes {
             d[j][e] = (g0 + e < n) ? static_cast<const float*>(s.pl[j])[g0 + e] : 0.0f;
         }
     }
+  }
+
+  // The same in two steps (raw 16-byte vectors first; see RawVec).
+  typedef s3a_u4 Raw[3];
+  __device__ static inline void fetch(const SrcCtx<DT>& s, int64_t g0, int64_t n, Raw& r) {
+    if (g0 + VEC <= n) {
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        if constexpr (BF)
+          r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint16_t*>(s.pl[j]) + g0));
+        else
+          r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u4*)(static_cast<const uint32_t*>(s.pl[j]) + g0));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 3; ++j)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          if constexpr (BF) {
+            const uint16_t* h = static_cast<const uint16_t*>(s.pl[j]);
+            const uint32_t a = (g0 + 2 * i < n) ? h[g0 + 2 * i] : 0u;
+            const uint32_t b = (g0 + 2 * i + 1 < n) ? h[g0 + 2 * i + 1] : 0u;
+            r[j][i] = a | (b << 16);
+          } else {
+            r[j][i] = (g0 + i < n) ? static_cast<const uint32_t*>(s.pl[j])[g0 + i] : 0u;
+          }
+        }
+    }
+  }
+  __device__ static inline void unpack(const Raw& r, float (&d)[3][VEC]) {
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        if constexpr (BF) {
+          d[j][2 * i] = __uint_as_float(r[j][i] << 16);
+          d[j][2 * i + 1] = __uint_as_float(r[j][i] & 0xffff0000u);
+        } else {
+          d[j][i] = __uint_as_float(r[j][i]);
+        }
+      }
   }
 
   // frame, row and column of element g0 (elements before the pair count as its first pixel)
@@ -468,14 +597,16 @@ __device__ inline void block_store_f64(double (&acc)[N], double (*red)[NSTAT], d
 // ---------------------------------------------------------------- tile bodies
 
 // One point of the Gauss-Newton statistics: centred model point y, residual
-// r, weight w (0 for masked points); Huber weight branch-free.
+// r, weight w (0 for masked points); Huber weight branch-free. COST: also the
+// cost and inlier count (statistics 17 and 18), which only the pass at the
+// last linearisation point reports; the other passes leave them at zero.
+template <bool COST = true>
 __device__ inline void gn_point(float (&a)[NSTAT], float y0, float y1, float y2, float r0, float r1, float r2, float w,
                                 float d2, float delta, float hd2) {
   const float e2 = fmaf(r0, r0, fmaf(r1, r1, r2 * r2));
   const float ie = __builtin_amdgcn_rsqf(e2);
   const bool inl = e2 <= d2;
   const float psi = inl ? 1.0f : delta * ie;
-  const float rho = inl ? 0.5f * e2 : fmaf(delta * e2, ie, -hd2);
   const float om = w * psi;
   const float oy0 = om * y0, oy1 = om * y1, oy2 = om * y2;
   a[0] += om;
@@ -487,15 +618,18 @@ __device__ inline void gn_point(float (&a)[NSTAT], float y0, float y1, float y2,
   a[14] = fmaf(oy2, r0, fmaf(-oy0, r2, a[14]));
   a[15] = fmaf(oy0, r1, fmaf(-oy1, r0, a[15]));
   a[16] = fmaf(oy0, r0, fmaf(oy1, r1, fmaf(oy2, r2, a[16])));
-  a[17] = fmaf(w, rho, a[17]);
-  a[18] += (inl && w > 0.0f) ? 1.0f : 0.0f;
+  if constexpr (COST) {
+    const float rho = inl ? 0.5f * e2 : fmaf(delta * e2, ie, -hd2);
+    a[17] = fmaf(w, rho, a[17]);
+    a[18] += (inl && w > 0.0f) ? 1.0f : 0.0f;
+  }
 }
 
 // Gauss-Newton pass over a depth tile that lies in one frame: the pair's
 // current similarity is folded into each side's camera once per tile, so a
 // pixel costs one affine map per side on its ray:
 //   y_c = d_p (A ray_p) + b,  A = sR R_p, b = sR t_p + t - c;   q_c = d_q (R_q ray_q) + t_q - c.
-template <int DT, int WG, int ITEMS>
+template <int DT, int WG, int ITEMS, bool COST>
 __device__ inline void tile_gn_depth_frame(const Shape& sh, const SrcCtx<DT>& src, const TileDesc& td,
                                            const PointParams& P, float (&a)[NSTAT]) {
   using L = DepthPlanes<DT>;
@@ -515,12 +649,11 @@ __device__ inline void tile_gn_depth_frame(const Shape& sh, const SrcCtx<DT>& sr
   const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
   const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
   const bool check_finite = P.nonfinite != 0;
-#pragma unroll 1
-  for (int it = 0; it < ITEMS; ++it) {
-    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
-    if (rel0 >= end_rel) break;
+  pipelined_items<WG, ITEMS, VEC, typename L::Raw>(
+      end_rel, [&](int rel, typename L::Raw& r) { L::fetch(src, td.begin + rel, sh.n_points, r); },
+      [&](const typename L::Raw& raw, int rel0) {
     float d[3][VEC];
-    L::load_raw(src, td.begin + rel0, sh.n_points, d);
+    L::unpack(raw, d);
     int f, row, col;
     L::position(src, td.begin + rel0, f, row, col);
 #pragma unroll
@@ -544,10 +677,10 @@ __device__ inline void tile_gn_depth_frame(const Shape& sh, const SrcCtx<DT>& sr
         y[i] = ok ? y[i] : 0.0f;
         q[i] = ok ? q[i] : 0.0f;
       }
-      gn_point(a, y[0], y[1], y[2], y[0] - q[0], y[1] - q[1], y[2] - q[2], w, d2, delta, hd2);
+      gn_point<COST>(a, y[0], y[1], y[2], y[0] - q[0], y[1] - q[1], y[2] - q[2], w, d2, delta, hd2);
       if (rel0 + e >= lo_rel) L::advance(src, f, row, col);
     }
-  }
+  });
 }
 
 
@@ -555,12 +688,56 @@ __device__ inline void tile_gn_depth_frame(const Shape& sh, const SrcCtx<DT>& sr
 // coordinates centred on the pair's centre c (the weighted target centroid):
 //   y_c = Mf p + (t - c),  q_c = q - c,  r = y_c - q_c,
 // so no product or difference involves coordinates far from the data, and the
-// 17 statistics plus cost and inlier count accumulate per lane over the few
-// points the lane handles in this tile (then pairwise across lanes, FP64
-// across wavefronts and tiles). Points outside the pair's range, below the
-// confidence threshold, or (in pairs that hold any) with a NaN/Inf value get
-// zero weight and zeroed coordinates.
-template <int DT, int WG, int ITEMS>
+// 17 statistics (plus cost and inlier count when COST) accumulate per lane
+// over the few points the lane handles in this tile (then pairwise across
+// lanes, FP64 across wavefronts and tiles). Points outside the pair's range,
+// below the confidence threshold, or (in pairs that hold any) with a NaN/Inf
+// value get zero weight and zeroed coordinates.
+// Elements of a raw vector that lie outside the pair's range [lo_rel, end_rel),
+// or (check_finite) hold a NaN/Inf in any plane, are zeroed in place: zero
+// weight and zero coordinates. Both cases are rare (a pair's first and last
+// vectors; pairs the moments pass found non-finite values in), so the common
+// vector pays one uniform test each.
+template <int DT>
+__device__ inline void mask_raw(RawVec& r, int rel0, int lo_rel, int end_rel, bool check_finite) {
+  constexpr int VEC = Planes<DT>::VEC;
+  if (rel0 < lo_rel || rel0 + VEC > end_rel) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) Planes<DT>::keep_elem(r, e, rel0 + e >= lo_rel && rel0 + e < end_rel);
+  }
+  if (check_finite) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      bool fin = true;
+#pragma unroll
+      for (int j = 0; j < 7; ++j) fin = fin && Planes<DT>::elem_finite(r, j, e);
+      Planes<DT>::keep_elem(r, e, fin);
+    }
+  }
+}
+
+template <int DT, bool COST>
+__device__ inline void gn_vector(const Shape& sh, const PointParams& P, RawVec& r, int rel0, int lo_rel,
+                                 int end_rel, bool check_finite, float (&a)[NSTAT]) {
+  constexpr int VEC = Planes<DT>::VEC;
+  using L = Planes<DT>;
+  const float tau = sh.tau, delta = sh.delta_f;
+  const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
+  mask_raw<DT>(r, rel0, lo_rel, end_rel, check_finite);
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) {
+    const float px = L::elem(r, 0, e), py = L::elem(r, 1, e), pz = L::elem(r, 2, e);
+    const float c = L::elem(r, 6, e);
+    const float w = c >= tau ? c : 0.0f;
+    const float y0 = fmaf(P.Mf[0], px, fmaf(P.Mf[1], py, fmaf(P.Mf[2], pz, P.tcf[0])));
+    const float y1 = fmaf(P.Mf[3], px, fmaf(P.Mf[4], py, fmaf(P.Mf[5], pz, P.tcf[1])));
+    const float y2 = fmaf(P.Mf[6], px, fmaf(P.Mf[7], py, fmaf(P.Mf[8], pz, P.tcf[2])));
+    gn_point<COST>(a, y0, y1, y2, y0 - (L::elem(r, 3, e) - P.cf[0]), y1 - (L::elem(r, 4, e) - P.cf[1]),
+                   y2 - (L::elem(r, 5, e) - P.cf[2]), w, d2, delta, hd2);
+  }
+}
+
+template <int DT, int WG, int ITEMS, bool COST>
 __device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td, const PointParams& P,
                                double (*red)[NSTAT], double* out) {
   constexpr int VEC = Planes<DT>::VEC;
@@ -569,50 +746,43 @@ __device__ inline void tile_gn(const Shape& sh, const SrcCtx<DT>& pl, const Tile
   for (int j = 0; j < NSTAT; ++j) a[j] = 0.0f;
   if constexpr (DT == DT_DEPTH_F32 || DT == DT_DEPTH_BF16) {
     if (P.active && pl.frame >= 0) {
-      tile_gn_depth_frame<DT, WG, ITEMS>(sh, pl, td, P, a);
+      tile_gn_depth_frame<DT, WG, ITEMS, COST>(sh, pl, td, P, a);
       block_store_f32<WG>(a, red, out);
       return;
     }
   }
   if (P.active) {
-    const float tau = sh.tau, delta = sh.delta_f;
-    const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
     const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
     const bool check_finite = P.nonfinite != 0;
+    if constexpr (DT == S3A_F32 || DT == S3A_BF16) {
+      pipelined_items<WG, ITEMS, VEC, RawVec>(
+          end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(pl, td.begin + rel, sh.n_points, r); },
+          [&](RawVec& r, int rel0) { gn_vector<DT, COST>(sh, P, r, rel0, lo_rel, end_rel, check_finite, a); });
+    } else {
+      // depth input whose tile spans frames: unprojected per element (DepthPlanes::load)
+      const float tau = sh.tau, delta = sh.delta_f;
+      const float d2 = delta * delta, hd2 = 0.5f * delta * delta;
 #pragma unroll 1
-    for (int it = 0; it < ITEMS; ++it) {
-      const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
-      if (rel0 >= end_rel) break;
-      float v[7][VEC];
-      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
-      if (rel0 < lo_rel || rel0 + VEC > end_rel) {  // boundary vector: zero foreign elements
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
-#pragma unroll
-          for (int j = 0; j < 7; ++j) v[j][e] = in ? v[j][e] : 0.0f;
-        }
-      }
-      if (check_finite) {
+      for (int it = 0; it < ITEMS; ++it) {
+        const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+        if (rel0 >= end_rel) break;
+        float v[7][VEC];
+        Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           float x[7];
 #pragma unroll
           for (int j = 0; j < 7; ++j) x[j] = v[j][e];
-          const bool fin = finite7(x);
+          const bool keep = rel0 + e >= lo_rel && rel0 + e < end_rel && (!check_finite || finite7(x));
 #pragma unroll
-          for (int j = 0; j < 7; ++j) v[j][e] = fin ? v[j][e] : 0.0f;
+          for (int j = 0; j < 7; ++j) x[j] = keep ? x[j] : 0.0f;
+          const float w = x[6] >= tau ? x[6] : 0.0f;
+          const float y0 = fmaf(P.Mf[0], x[0], fmaf(P.Mf[1], x[1], fmaf(P.Mf[2], x[2], P.tcf[0])));
+          const float y1 = fmaf(P.Mf[3], x[0], fmaf(P.Mf[4], x[1], fmaf(P.Mf[5], x[2], P.tcf[1])));
+          const float y2 = fmaf(P.Mf[6], x[0], fmaf(P.Mf[7], x[1], fmaf(P.Mf[8], x[2], P.tcf[2])));
+          gn_point<COST>(a, y0, y1, y2, y0 - (x[3] - P.cf[0]), y1 - (x[4] - P.cf[1]), y2 - (x[5] - P.cf[2]), w,
+                         d2, delta, hd2);
         }
-      }
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        const float px = v[0][e], py = v[1][e], pz = v[2][e];
-        const float w = v[6][e] >= tau ? v[6][e] : 0.0f;
-        const float y0 = fmaf(P.Mf[0], px, fmaf(P.Mf[1], py, fmaf(P.Mf[2], pz, P.tcf[0])));
-        const float y1 = fmaf(P.Mf[3], px, fmaf(P.Mf[4], py, fmaf(P.Mf[5], pz, P.tcf[1])));
-        const float y2 = fmaf(P.Mf[6], px, fmaf(P.Mf[7], py, fmaf(P.Mf[8], pz, P.tcf[2])));
-        gn_point(a, y0, y1, y2, y0 - (v[3][e] - P.cf[0]), y1 - (v[4][e] - P.cf[1]), y2 - (v[5][e] - P.cf[2]), w,
-                 d2, delta, hd2);
       }
     }
   }
@@ -634,12 +804,11 @@ __device__ inline void tile_moments_depth_frame(const Shape& sh, const SrcCtx<DT
   const DepthCam& cq = src.cq;
   const float tau = sh.tau;
   const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
-#pragma unroll 1
-  for (int it = 0; it < ITEMS; ++it) {
-    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
-    if (rel0 >= end_rel) break;
+  pipelined_items<WG, ITEMS, VEC, typename L::Raw>(
+      end_rel, [&](int rel, typename L::Raw& r) { L::fetch(src, td.begin + rel, sh.n_points, r); },
+      [&](const typename L::Raw& raw, int rel0) {
     float d[3][VEC];
-    L::load_raw(src, td.begin + rel0, sh.n_points, d);
+    L::unpack(raw, d);
     int f, row, col;
     L::position(src, td.begin + rel0, f, row, col);
     float s[17];
@@ -681,7 +850,7 @@ __device__ inline void tile_moments_depth_frame(const Shape& sh, const SrcCtx<DT
     }
 #pragma unroll
     for (int j = 1; j < 17; ++j) a[j] += (double)s[j];
-  }
+  });
   // to the submap frame: x = x' + tp, y = y' + tq
   const double tp[3] = {cp.t[0], cp.t[1], cp.t[2]}, tq[3] = {cq.t[0], cq.t[1], cq.t[2]};
   const double W = a[0], Sx[3] = {a[1], a[2], a[3]}, Sy[3] = {a[4], a[5], a[6]};
@@ -719,35 +888,52 @@ __device__ inline void tile_moments(const Shape& sh, const SrcCtx<DT>& pl, const
       return;
     }
   }
+  // one point: validity (counted), then the weighted raw moments in FP64
+  auto point = [&](float (&x)[7], bool in) {
+    const bool fin = finite7(x);
+    const bool valid = in && fin && x[6] >= tau;
+    nvalid += valid ? 1 : 0;
+    nbad += (in && !fin) ? 1 : 0;
+#pragma unroll
+    for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;
+    const double w = x[6];
+    const double p0 = x[0], p1 = x[1], p2 = x[2], q0 = x[3], q1 = x[4], q2 = x[5];
+    const double wp0 = w * p0, wp1 = w * p1, wp2 = w * p2;
+    const double wq0 = w * q0, wq1 = w * q1, wq2 = w * q2;
+    a[0] += w;
+    a[1] += wp0; a[2] += wp1; a[3] += wp2;
+    a[4] += wq0; a[5] += wq1; a[6] += wq2;
+    a[7] = fma(wp0, p0, fma(wp1, p1, fma(wp2, p2, a[7])));
+    a[8] = fma(wq0, p0, a[8]);  a[9] = fma(wq0, p1, a[9]);  a[10] = fma(wq0, p2, a[10]);
+    a[11] = fma(wq1, p0, a[11]); a[12] = fma(wq1, p1, a[12]); a[13] = fma(wq1, p2, a[13]);
+    a[14] = fma(wq2, p0, a[14]); a[15] = fma(wq2, p1, a[15]); a[16] = fma(wq2, p2, a[16]);
+  };
+  if constexpr (DT == S3A_F32 || DT == S3A_BF16) {
+    pipelined_items<WG, ITEMS, VEC, RawVec>(
+        end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(pl, td.begin + rel, sh.n_points, r); },
+        [&](RawVec& r, int rel0) {
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) {
+            float x[7];
+#pragma unroll
+            for (int j = 0; j < 7; ++j) x[j] = Planes<DT>::elem(r, j, e);
+            point(x, rel0 + e >= lo_rel && rel0 + e < end_rel);
+          }
+        });
+  } else {
 #pragma unroll 1
-  for (int it = 0; it < ITEMS; ++it) {
-    const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
-    if (rel0 >= end_rel) break;
-    float v[7][VEC];
-    Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
+    for (int it = 0; it < ITEMS; ++it) {
+      const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
+      if (rel0 >= end_rel) break;
+      float v[7][VEC];
+      Planes<DT>::load(pl, td.begin + rel0, sh.n_points, v);
 #pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const bool in = rel0 + e >= lo_rel && rel0 + e < end_rel;
-      float x[7];
+      for (int e = 0; e < VEC; ++e) {
+        float x[7];
 #pragma unroll
-      for (int j = 0; j < 7; ++j) x[j] = v[j][e];
-      const bool fin = finite7(x);
-      const bool valid = in && fin && x[6] >= tau;
-      nvalid += valid ? 1 : 0;
-      nbad += (in && !fin) ? 1 : 0;
-#pragma unroll
-      for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;
-      const double w = x[6];
-      const double p0 = x[0], p1 = x[1], p2 = x[2], q0 = x[3], q1 = x[4], q2 = x[5];
-      const double wp0 = w * p0, wp1 = w * p1, wp2 = w * p2;
-      const double wq0 = w * q0, wq1 = w * q1, wq2 = w * q2;
-      a[0] += w;
-      a[1] += wp0; a[2] += wp1; a[3] += wp2;
-      a[4] += wq0; a[5] += wq1; a[6] += wq2;
-      a[7] = fma(wp0, p0, fma(wp1, p1, fma(wp2, p2, a[7])));
-      a[8] = fma(wq0, p0, a[8]);  a[9] = fma(wq0, p1, a[9]);  a[10] = fma(wq0, p2, a[10]);
-      a[11] = fma(wq1, p0, a[11]); a[12] = fma(wq1, p1, a[12]); a[13] = fma(wq1, p2, a[13]);
-      a[14] = fma(wq2, p0, a[14]); a[15] = fma(wq2, p1, a[15]); a[16] = fma(wq2, p2, a[16]);
+        for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+        point(x, rel0 + e >= lo_rel && rel0 + e < end_rel);
+      }
     }
   }
   a[17] = (double)nvalid;
@@ -786,7 +972,9 @@ template <int DT, int MODE, int WG, int ITEMS>
 __device__ inline void tile_body(const Shape& sh, const SrcCtx<DT>& pl, const TileDesc& td,
                                  const PointParams& P, double (*red)[NSTAT], double* out) {
   if constexpr (MODE == MODE_GN) {
-    tile_gn<DT, WG, ITEMS>(sh, pl, td, P, red, out);
+    tile_gn<DT, WG, ITEMS, true>(sh, pl, td, P, red, out);
+  } else if constexpr (MODE == MODE_GN_NC) {
+    tile_gn<DT, WG, ITEMS, false>(sh, pl, td, P, red, out);
   } else if constexpr (MODE == MODE_MOMENTS) {
     tile_moments<DT, WG, ITEMS>(sh, pl, td, red, out);
   } else {

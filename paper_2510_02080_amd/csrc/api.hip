@@ -299,7 +299,7 @@ hipError_t enqueue_batched_multi(s3a_handle* h, int dtype, const LaunchCfg& lc, 
   const int grid = grid_for(h, lc, mt);
   const int npass = 1 + sh.K + ((sh.flags & S3A_FLAG_FINAL_COST) ? 1 : 0);
   for (int pass = 0; pass < npass; ++pass) {
-    const int mode = pass == 0 ? MODE_MOMENTS : MODE_GN;
+    const int mode = pass_mode(pass, sh.K);
     {
       TimedLaunch tl(h, st);
       e = launch_pass(dtype, mode, lc, sh, dcd, h->w, 0, -1, grid, st);
@@ -434,7 +434,7 @@ int align_run(s3a_handle* h, const s3a_align_desc* d, const s3a_depth_pair* dept
     for (int k = 0; k < d->n_pairs; ++k) {
       const PairSched& s = sched[k];
       for (int pass = 0; pass < npass; ++pass) {
-        const int mode = pass == 0 ? MODE_MOMENTS : MODE_GN;
+        const int mode = pass_mode(pass, sh.K);
         {
           TimedLaunch tl(h, st);
           S3A_TRY(launch_pass(d->dtype, mode, lc, sh, dcd, h->w, s.tile0, s.tile0 + s.ntiles, s.ntiles, st));
@@ -617,7 +617,7 @@ int s3a_align_pairs_noalloc(const s3a_align_desc* d, const s3a_sim3* init, s3a_s
   const int grid = (int)std::max<int64_t>(mt, 1);
   const int npass = 1 + sh.K + ((sh.flags & S3A_FLAG_FINAL_COST) ? 1 : 0);
   for (int pass = 0; pass < npass; ++pass) {
-    e = launch_pass(d->dtype, pass == 0 ? MODE_MOMENTS : MODE_GN, lc, sh, dcd, w, 0, -1, grid, st);
+    e = launch_pass(d->dtype, pass_mode(pass, sh.K), lc, sh, dcd, w, 0, -1, grid, st);
     if (e != hipSuccess) return hip_fail(nullptr, e);
     e = launch_finalize(pass == 0 ? 0 : (pass <= sh.K ? 1 : 2), sh, dcd, w, pass, 0, sh.n_pairs, st);
     if (e != hipSuccess) return hip_fail(nullptr, e);

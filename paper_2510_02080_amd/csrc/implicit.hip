@@ -54,17 +54,15 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
 #pragma unroll
     for (int j = 0; j < HSTAT; ++j) a[j] = 0.0;
     const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
-#pragma unroll 1
-    for (int it = 0; it < ITEMS; ++it) {
-      const int rel0 = (it * WG + (int)threadIdx.x) * VEC;
-      if (rel0 >= end_rel) break;
-      float v[7][VEC];
-      Planes<DT>::load(SrcCtx<DT>{pl}, td.begin + rel0, sh.n_points, v);
+    const SrcCtx<DT> src{pl};
+    pipelined_items<WG, ITEMS, VEC, RawVec>(
+        end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(src, td.begin + rel, sh.n_points, r); },
+        [&](const RawVec& raw, int rel0) {
 #pragma unroll
       for (int e = 0; e < VEC; ++e) {
         float x[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) x[j] = v[j][e];
+        for (int j = 0; j < 7; ++j) x[j] = Planes<DT>::elem(raw, j, e);
         const bool valid = P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
 #pragma unroll
         for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;  // masked points add zeros
@@ -104,7 +102,7 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
         a[50] += c;
         a[51] += valid ? 1.0 : 0.0;
       }
-    }
+    });
     block_store_h<WG>(a, red, hpart + (int64_t)t * HSTAT);
   }
 }

@@ -107,6 +107,7 @@ __global__ __launch_bounds__(WG, 2) void k_persistent(Shape sh, const CallDesc* 
     const PointParams P = load_params(w.params + j);
     double* out = w.partials + (int64_t)t * NSTAT;
     if (pass == 0) tile_body<DT, MODE_MOMENTS, WG, ITEMS>(sh, SrcCtx<DT>{pl}, td, P, red, out);
+    else if (pass < sh.K) tile_body<DT, MODE_GN_NC, WG, ITEMS>(sh, SrcCtx<DT>{pl}, td, P, red, out);
     else tile_body<DT, MODE_GN, WG, ITEMS>(sh, SrcCtx<DT>{pl}, td, P, red, out);
     if (threadIdx.x == 0) {
       __threadfence();  // partials before the arrival

@@ -21,7 +21,14 @@ constexpr int NSTAT = 19;
 //   0 sum om, 1-3 sum om y_c, 4-9 sum om y_c y_c^T (xx xy xz yy yz zz),
 //   10-12 sum om r, 13-15 sum om y_c x r, 16 sum om y_c . r,
 //   17 sum w rho, 18 inlier count.
-enum PassMode { MODE_MOMENTS = 0, MODE_GN = 1, MODE_COST = 2, MODE_ADJOINT = 3 };
+// MODE_GN_NC: a Gauss-Newton pass whose cost and inlier count (17, 18) are not
+// needed (every pass but the one at the last linearisation point): left zero.
+enum PassMode { MODE_MOMENTS = 0, MODE_GN = 1, MODE_COST = 2, MODE_ADJOINT = 3, MODE_GN_NC = 4 };
+
+// Mode of pass `pass` (0: moments, 1..K: Gauss-Newton, K+1: final cost) of a call with K steps.
+__host__ __device__ inline int pass_mode(int pass, int K) {
+  return pass == 0 ? MODE_MOMENTS : (pass < K ? MODE_GN_NC : MODE_GN);
+}
 
 // A pair's first tile starts at a multiple of 64 elements (its head is masked),
 // and tiles hold a multiple of 64 elements, so every tile boundary inside a pair
