@@ -51,16 +51,15 @@ EDGE_INFO_SCALE = 1.0 / 0.01 ** 2
 PGO_HUBER = 3.75
 
 # HBM traffic of the roofline kernel (k_pass, FP32, 256-pair batch) per pass
-# launch, averaged over the step's moments pass and 10 Gauss-Newton passes: the
+# launch, averaged over the call's moments pass and 10 Gauss-Newton passes: the
 # FETCH_SIZE and WRITE_SIZE counters of two rocprofv3 --pmc runs, FETCH_SIZE
 # scaled by what it reads for a plain 1 GiB copy (about 2: it counts half the
 # bytes on this part; WRITE_SIZE reads exactly). The figures and commands are
 # in profiles/k_pass_fp32_256pairs_32M_hbm_counters.md. They hold only for the
 # sources and launch shapes they were taken with: otherwise the bench reports null.
 KPASS_SOURCES = ("align.hip", "align_kernels.h", "align_launch.h", "s3a_internal.h", "dmath.h")
-MEASURED_TRAFFIC = {"sources_sha256": "e6c050ca007eca4f09a2a94c5a2f9b067c1d04a45242bb3815108f6809cfd5dd",
-                    "bytes_per_launch": {(256, 2, 0): 904030626, (256, 4, 0): 901645575, (256, 8, 0): 900400206,
-                                         (512, 2, 0): 901648649, (512, 4, 0): 900401258}}
+MEASURED_TRAFFIC = {"sources_sha256": "b458cd5aae0f80a46ebefb9778683c12c8ce6b9126e20aa7a084085aab9fa3a4",
+                    "bytes_per_launch": {(512, 2, 0): 901680470, (512, 4, 0): 900432199, (256, 4, 0): 901688486}}
 
 
 def kpass_sources_sha256():
