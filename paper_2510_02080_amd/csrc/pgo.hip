@@ -13,10 +13,11 @@
 // symbolic block Cholesky (column structures, elimination tree, levels), and
 // fixed-order lists: which edges assemble into which block, and which pairs of
 // factor blocks update which target block.
-// Device, per iteration: one kernel linearises every edge (one lane per edge);
-// one workgroup then assembles H and g, factorises level by level (blocks of a
-// level are independent), solves L L^T dx = -g level by level, and applies
-// T <- Exp(dx) T. All waits are workgroup barriers.
+// Device, per iteration: the edges are linearised and H and g assembled across
+// the chip; the sparse columns are factored level by level, two launches per
+// level spread over the chip (the columns of a level are independent); the
+// dense trailing clique is factored by one workgroup on the matrix cores; one
+// workgroup solves L L^T dx = -g and applies T <- Exp(dx) T.
 #include <string.h>
 
 #include <algorithm>
@@ -52,19 +53,19 @@ struct PgoDev {
   // -= L_a L_b^T for (a, b) in up_a/up_b[up_ptr[t]..]; a, b index blocks (always off-diagonal)
   const int32_t* up_ptr; const int32_t* up_a; const int32_t* up_b;
   // schedule of the sparse part (columns below p0), for the factorisation and both
-  // solves: per level its columns, the update targets that receive updates (diagonal
-  // c or m + off-diagonal block) and the off-diagonal blocks; for the column at
-  // schedule position j, its row blocks fs_blk[fs_ptr[j]..] (forward solve) and its
-  // column blocks bs_blk[bs_ptr[j]..] (backward solve), consecutive over a level
+  // solves: the columns of level l are flev_col[flev_ptr[l] .. flev_ptr[l+1]); for the
+  // column at schedule position j, its targets that receive updates (its diagonal c or
+  // m + one of its off-diagonal blocks) lt_tgt[ct_ptr[j] .. ct_ptr[j+1]), its row
+  // blocks fs_blk[fs_ptr[j]..] (forward solve) and its column blocks bs_blk[bs_ptr[j]..]
+  // (backward solve)
   int32_t nflev;
   const int32_t* flev_ptr; const int32_t* flev_col;
-  // the level's update pairs, target by target in lt_tgt order: target at position i
-  // gets -= L_a L_b^T for (a, b) in fu_a/fu_b[fu_ptr[i]..fu_ptr[i+1])
+  const int32_t* lt_tgt; const int32_t* ct_ptr;
+  // the update pairs target by target in lt_tgt order: target at position i gets
+  // -= L_a L_b^T for (a, b) in fu_a/fu_b[fu_ptr[i]..fu_ptr[i+1])
   const int32_t* fu_ptr; const int32_t* fu_a; const int32_t* fu_b;
   const int32_t* fs_ptr; const int32_t* fs_blk;
   const int32_t* bs_ptr; const int32_t* bs_blk;
-  const int32_t* lt_ptr; const int32_t* lt_tgt;
-  const int32_t* lb_ptr; const int32_t* lb_blk;
   // dense trailing clique: columns p0 .. m-1 (K of them) hold every block below the
   // diagonal. Its blocks, with the updates of the sparse columns applied (dt lists),
   // form the dense front F (order nF = 7 K padded with identity to a multiple of the
@@ -442,86 +443,52 @@ __global__ __launch_bounds__(256) void k_pgo_assemble(PgoDev d, double lambda, i
   }
 }
 
-// chi^2 at the linearisation point, then (update) the sparse columns' factorisation
-// level by level, by one workgroup.
-// Update products of one factor level kept in LDS at a time.
-constexpr int UPD_CHUNK = 256;
-
-__global__ __launch_bounds__(PGO_WG) void k_pgo_factor(PgoDev d, int it, int update) {
+// chi^2 at the linearisation point (fixed order), by one workgroup.
+__global__ __launch_bounds__(PGO_WG) void k_pgo_chi2(PgoDev d, int it) {
   __shared__ double sh[PGO_WG / 64 + 1];
-  __shared__ int s_fail;
-  __shared__ double prod[49 * UPD_CHUNK];
-  const int tid = threadIdx.x;
   if (*d.status != 0) return;
   double part = 0.0;
-  for (int k = tid; k < d.n_edges; k += PGO_WG) part += d.r2[k];
-  const double c2 = wg_sum<PGO_WG>(part, sh);  // fixed order
-  if (tid == 0) d.chi2[it] = c2;
-  if (!update) return;
-  if (tid == 0) s_fail = 0;
-  __syncthreads();
-  // ---- factorisation of the sparse columns, level by level
-  for (int l = 0; l < d.nflev; ++l) {
-    const int c0 = d.flev_ptr[l], c1 = d.flev_ptr[l + 1];
-    // (A) the updates of this level's targets (diagonal and off-diagonal blocks of its
-    // columns), in chunks of UPD_CHUNK pairs: every product row L_a(r,:) L_b^T by one
-    // thread into LDS, then one thread per (target, row) subtracts its products' sum
-    // (list order, chunk after chunk)
-    {
-      const int i0 = d.lt_ptr[l], i1 = d.lt_ptr[l + 1];
-      const int q0 = d.fu_ptr[i0], q1 = d.fu_ptr[i1];
-      for (int base = q0; base < q1; base += UPD_CHUNK) {
-        const int top = min(base + UPD_CHUNK, q1);
-        for (int it = tid; it < (top - base) * 7; it += PGO_WG) {
-          const int q = base + it / 7, r = it % 7;
-          const double* La = d.Lb + 49 * d.fu_a[q] + 7 * r;
-          const double* LB = d.Lb + 49 * d.fu_b[q];
-          double a[7];
-#pragma unroll
-          for (int u = 0; u < 7; ++u) a[u] = La[u];
-#pragma unroll
-          for (int c = 0; c < 7; ++c) {
-            double t = 0.0;
-#pragma unroll
-            for (int u = 0; u < 7; ++u) t += a[u] * LB[7 * c + u];
-            prod[49 * (q - base) + 7 * r + c] = t;
-          }
-        }
-        __syncthreads();
-        for (int it = tid; it < (i1 - i0) * 7; it += PGO_WG) {
-          const int i = i0 + it / 7, r = it % 7;
-          const int lo = max(d.fu_ptr[i], base), hi = min(d.fu_ptr[i + 1], top);
-          if (lo >= hi) continue;
-          const int t = d.lt_tgt[i];
-          double* T = (t < d.m ? d.Ld + 49 * t : d.Lb + 49 * (t - d.m)) + 7 * r;
-#pragma unroll
-          for (int c = 0; c < 7; ++c) {
-            double acc = 0.0;
-            for (int q = lo; q < hi; ++q) acc += prod[49 * (q - base) + 7 * r + c];
-            T[c] -= acc;
-          }
-        }
-        __syncthreads();
-      }
-    }
-    // (B) Cholesky of each diagonal block of the level (and its inverse): one lane per block
-    for (int cc = c0 + tid; cc < c1; cc += PGO_WG) {
-      const int col = d.flev_col[cc];
-      if (!chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, nullptr)) s_fail = 1;
-    }
+  for (int k = threadIdx.x; k < d.n_edges; k += PGO_WG) part += d.r2[k];
+  const double c2 = wg_sum<PGO_WG>(part, sh);
+  if (threadIdx.x == 0) d.chi2[it] = c2;
+}
+
+// One level of the sparse factorisation spread over the chip, in two launches
+// (the columns of a level are independent):
+//  k_pgo_level_updates: every target of the level's columns (a diagonal block or
+//    an off-diagonal block that receives updates) takes its updates L_a L_b^T from
+//    the factored columns below, one wavefront per target across the chip;
+//  k_pgo_level_factor: a workgroup per column; one lane factors and inverts the
+//    diagonal block, and one thread per row forms the off-diagonal rows
+//    L_ij = S_ij L_jj^{-T}.
+constexpr int LEV_WG = 256;
+__global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
+  if (*d.status != 0) return;
+  const int lane = threadIdx.x & 63;
+  const int i0 = d.ct_ptr[d.flev_ptr[l]], i1 = d.ct_ptr[d.flev_ptr[l + 1]];
+  const int waves = (int)gridDim.x * (LEV_WG / 64);
+  for (int i = i0 + (int)blockIdx.x * (LEV_WG / 64) + ((int)threadIdx.x >> 6); i < i1; i += waves) {
+    double* e = target_elem(d, d.lt_tgt[i], lane);
+    update_target(d, e, e, d.fu_ptr[i], d.fu_ptr[i + 1], d.fu_a, d.fu_b, lane);
+  }
+}
+
+__global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
+  if (*d.status != 0) return;
+  __shared__ int s_fail;
+  for (int j = d.flev_ptr[l] + (int)blockIdx.x; j < d.flev_ptr[l + 1]; j += (int)gridDim.x) {
+    const int col = d.flev_col[j];
+    if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, nullptr) ? 0 : 1;
     __syncthreads();
-    if (s_fail) break;
-    // (C) L_ij = S_ij L_jj^{-T} for every off-diagonal block of this level: one lane per block row
-    {
-      const int b0 = d.lb_ptr[l], nb = d.lb_ptr[l + 1] - b0;
-      for (int x = tid; x < nb * 7; x += PGO_WG) {
-        const int bb = d.lb_blk[b0 + x / 7];
-        trsm_row(d.Lb + 49 * bb + 7 * (x % 7), d.Di + 49 * d.blk_col[bb], nullptr);
-      }
+    if (s_fail) {
+      if (threadIdx.x == 0) *d.status = 2;
+      return;
     }
+    const int b0 = d.col_ptr[col], nb = d.col_ptr[col + 1] - b0;
+    for (int x = (int)threadIdx.x; x < 7 * nb; x += LEV_WG)
+      trsm_row(d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7), d.Di + 49 * col, nullptr);
     __syncthreads();
   }
-  if (s_fail && tid == 0) *d.status = 2;
 }
 
 // The clique's blocks with the sparse columns' updates applied, written into the
@@ -910,6 +877,7 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
 
 struct PgoWorkspace {
   int32_t n_nodes = -1, n_edges = -1, gauge = -1;
+  std::vector<int32_t> flev, ct;  // host copies of the sparse levels' column and target ranges (launch sizes)
   std::vector<int32_t> ij;  // topology the symbolic analysis was made for
   void* buf = nullptr;
   PgoDev dev{};
@@ -927,8 +895,8 @@ namespace {
 struct Symbolic {
   int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
-      up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_ptr, lt_tgt, lb_ptr, lb_blk, row_ptr, row_blk,
-      chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b;
+      up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_tgt, row_ptr, row_blk,
+      chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b, ct_ptr;
   std::vector<int8_t> gv_sign;
 };
 
@@ -1069,8 +1037,7 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   S.nF = K > 0 ? (7 * K + FT - 1) / FT * FT : 0;
   // schedule of the sparse columns (levels without one are dropped)
   S.flev_ptr.assign(1, 0);
-  S.lt_ptr.assign(1, 0);
-  S.lb_ptr.assign(1, 0);
+  S.ct_ptr.assign(1, 0);
   for (int l = 0; l < nlev; ++l) {
     bool any = false;
     for (int q = S.lev_ptr[l]; q < S.lev_ptr[l + 1]; ++q) {
@@ -1082,13 +1049,11 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
       if (has_updates(c)) S.lt_tgt.push_back(c);
       for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) {
         if (has_updates(m + b)) S.lt_tgt.push_back(m + b);
-        S.lb_blk.push_back(b);
       }
+      S.ct_ptr.push_back((int32_t)S.lt_tgt.size());
     }
     if (!any) continue;
     S.flev_ptr.push_back((int32_t)S.flev_col.size());
-    S.lt_ptr.push_back((int32_t)S.lt_tgt.size());
-    S.lb_ptr.push_back((int32_t)S.lb_blk.size());
   }
   S.nflev = (int)S.flev_ptr.size() - 1;
   // the clique: block map, and each of its targets' updates from sparse columns
@@ -1191,15 +1156,21 @@ namespace {
 // current linearisation): assembly across the chip, the sparse factorisation in one
 // workgroup, the clique's sparse-column updates across the chip, then the clique, the
 // solves and the update in one workgroup.
-hipError_t launch_iteration(const PgoDev& d, s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
-  if (!update || d.m == 0) {
-    hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(PGO_WG), 0, st, d, it, 0);
-    return hipGetLastError();
-  }
+hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, const std::vector<int32_t>& ct,
+                            s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
+  hipLaunchKernelGGL(k_pgo_chi2, dim3(1), dim3(PGO_WG), 0, st, d, it);
+  if (!update || d.m == 0) return hipGetLastError();
   const int64_t work = std::max<int64_t>((int64_t)d.nblk * 49, (int64_t)d.m * 49);
   const int ga = (int)std::min<int64_t>((work + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pgo_assemble, dim3(ga), dim3(256), 0, st, d, lambda, lm);
-  hipLaunchKernelGGL(k_pgo_factor, dim3(1), dim3(PGO_WG), 0, st, d, it, 1);
+  for (int l = 0; l + 1 < (int)flev.size(); ++l) {
+    const int ntgt = ct[flev[l + 1]] - ct[flev[l]], ncol = flev[l + 1] - flev[l];
+    if (ntgt > 0) {
+      const int g = std::min((ntgt + LEV_WG / 64 - 1) / (LEV_WG / 64), 1024);
+      hipLaunchKernelGGL(k_pgo_level_updates, dim3(g), dim3(LEV_WG), 0, st, d, l);
+    }
+    hipLaunchKernelGGL(k_pgo_level_factor, dim3(std::min(ncol, 1024)), dim3(LEV_WG), 0, st, d, l);
+  }
   if (d.K > 0) {
     hipLaunchKernelGGL(k_pgo_clique_updates, dim3((d.n_dt + 3) / 4), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_pgo_front, dim3(1), dim3(FRONT_WG), 0, st, d);
@@ -1253,7 +1224,7 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
       e = hipMemcpyAsync(ws->T_bak, T, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<uint32_t*>(cur.status), 1, st);
       if (e != hipSuccess) return fail(last_hip, e);
-      if ((e = launch_iteration(cur, T, lam, it, 1, 1, st)) != hipSuccess) return fail(last_hip, e);
+      if ((e = launch_iteration(cur, ws->flev, ws->ct, T, lam, it, 1, 1, st)) != hipSuccess) return fail(last_hip, e);
       int32_t fst = 0;
       double pred = 0.0;
       e = hipMemcpyAsync(&fst, cur.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -1442,8 +1413,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.flev_ptr.size()) + bytes_of<int32_t>(S.flev_col.size() + 1);
     total += bytes_of<int32_t>(S.dt_tgt.size() + 1) + bytes_of<int32_t>(S.dt_ptr.size());
     total += bytes_of<int32_t>(S.dup_a.size() + 1) * 2;
-    total += bytes_of<int32_t>(S.lt_ptr.size()) + bytes_of<int32_t>(S.lt_tgt.size() + 1);
-    total += bytes_of<int32_t>(S.lb_ptr.size()) + bytes_of<int32_t>(S.lb_blk.size() + 1);
+    total += bytes_of<int32_t>(S.lt_tgt.size() + 1) + bytes_of<int32_t>(S.ct_ptr.size());
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
     total += bytes_of<int32_t>(S.fu_ptr.size()) + bytes_of<int32_t>(S.fu_a.size() + 1) * 2;
@@ -1499,10 +1469,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_dtp = carve<int32_t>(c, S.dt_ptr.size()); put(p_dtp, S.dt_ptr); d.dt_ptr = p_dtp;
     int32_t* p_dua = carve<int32_t>(c, S.dup_a.size() + 1); put(p_dua, S.dup_a); d.dup_a = p_dua;
     int32_t* p_dub = carve<int32_t>(c, S.dup_b.size() + 1); put(p_dub, S.dup_b); d.dup_b = p_dub;
-    int32_t* p_ltp = carve<int32_t>(c, S.lt_ptr.size()); put(p_ltp, S.lt_ptr); d.lt_ptr = p_ltp;
     int32_t* p_ltt = carve<int32_t>(c, S.lt_tgt.size() + 1); put(p_ltt, S.lt_tgt); d.lt_tgt = p_ltt;
-    int32_t* p_lbp = carve<int32_t>(c, S.lb_ptr.size()); put(p_lbp, S.lb_ptr); d.lb_ptr = p_lbp;
-    int32_t* p_lbb = carve<int32_t>(c, S.lb_blk.size() + 1); put(p_lbb, S.lb_blk); d.lb_blk = p_lbb;
+    int32_t* p_ctp = carve<int32_t>(c, S.ct_ptr.size()); put(p_ctp, S.ct_ptr); d.ct_ptr = p_ctp;
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;
     int32_t* p_rwb = carve<int32_t>(c, S.row_blk.size()); put(p_rwb, S.row_blk); d.row_blk = p_rwb;
     int32_t* p_fsp = carve<int32_t>(c, S.fs_ptr.size()); put(p_fsp, S.fs_ptr); d.fs_ptr = p_fsp;
@@ -1551,6 +1519,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     ws->gauge = p.gauge;
     ws->ij.assign(ij, ij + 2 * (size_t)n_edges);
     ws->cap_iters = iters_cap;
+    ws->flev = S.flev_ptr;
+    ws->ct = S.ct_ptr;
     ws->nnz_blocks = (int64_t)nb + m;
   }
   PgoDev d = ws->dev;
@@ -1567,7 +1537,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
       if ((e = launch_linearize(d, T_meas, omega, T, p.huber_delta, !update, st)) != hipSuccess) return fail(last_hip, e);
     }
     if (update && d.m == 0) continue;
-    if ((e = launch_iteration(d, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
+    if ((e = launch_iteration(d, ws->flev, ws->ct, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
   }
   if (report) {
     std::vector<double> chi(p.iters + 1, 0.0);
