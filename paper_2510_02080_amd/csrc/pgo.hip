@@ -476,13 +476,53 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
 __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
   if (*d.status != 0) return;
   __shared__ int s_fail;
+  __shared__ double part[LEV_WG / 64][7];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = d.flev_ptr[l] + (int)blockIdx.x; j < d.flev_ptr[l + 1]; j += (int)gridDim.x) {
     const int col = d.flev_col[j];
     if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, nullptr) ? 0 : 1;
+    // forward solve of this column, y_c = L_cc^{-1} (y_c - sum_k L_ck y_k): its row blocks
+    // (c, k) lie in factored columns of lower levels, whose y_k are final; per-thread
+    // sums over the blocks (strided), then a fixed tree
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int q = d.fs_ptr[j] + (int)threadIdx.x; q < d.fs_ptr[j + 1]; q += LEV_WG) {
+      const int b = d.fs_blk[q];
+      const double* L = d.Lb + 49 * b;
+      const double* y = d.g + 7 * d.blk_col[b];
+      double yv[7];
+#pragma unroll
+      for (int u = 0; u < 7; ++u) yv[u] = y[u];
+#pragma unroll
+      for (int r = 0; r < 7; ++r)
+#pragma unroll
+        for (int u = 0; u < 7; ++u) acc[r] += L[7 * r + u] * yv[u];
+    }
+    wave_totals_f64(acc);
+    if (lane == 0)
+#pragma unroll
+      for (int r = 0; r < 7; ++r) part[wv][r] = acc[r];
     __syncthreads();
     if (s_fail) {
       if (threadIdx.x == 0) *d.status = 2;
       return;
+    }
+    if (threadIdx.x == 0) {
+      double v[7];
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < LEV_WG / 64; ++q) s += part[q][r];
+        v[r] = d.g[7 * col + r] - s;
+      }
+      const double* Di = d.Di + 49 * col;
+#pragma unroll
+      for (int r = 0; r < 7; ++r) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
+        d.g[7 * col + r] = t;
+      }
     }
     const int b0 = d.col_ptr[col], nb = d.col_ptr[col + 1] - b0;
     for (int x = (int)threadIdx.x; x < 7 * nb; x += LEV_WG)
@@ -788,8 +828,7 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
   const int tid = threadIdx.x;
   if (*d.status != 0) return;
   const int lane = tid & 63, wv = tid >> 6;
-  // ---- forward solve L y = -g over the sparse columns, levels from the leaves
-  for (int l = 0; l < d.nflev; ++l) solve_level<false>(d, l, prod);
+  // (the forward solve over the sparse columns ran with their factorisation, k_pgo_level_factor)
   if (d.K > 0) {
     const int n = d.nF, nK = 7 * d.K;
     // ---- the clique rows: y_i - sum over sparse columns k of L_ik y_k, into LDS
