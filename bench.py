@@ -267,15 +267,16 @@ def main():
     # ---- the same batch as one persistent launch (pass-major tickets), graph-captured, with its
     # own autotuned shape (workgroups per CU instead of one per tile); then back to the graph path's
     if "persistent" in legs:
-        graph_shape = h.get_tuning(s3a.F32, b2.n_points)
-        tune_p = None if args.no_autotune else h.autotune(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT)
+        retune = not args.no_autotune and not args.tuning
+        tune_p = h.autotune(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT) if retune else None
         Sp = torch.empty_like(S)
         stepp = lambda: h.align_pairs(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT, out=Sp, info=False)
         ms_p = timed(stepp, args.steps, args.warmup)
         kp, _ = kernel_ms(stepp, args.steps)
         Sp, ibp = h.align_pairs(pm, b2.tau, b2.delta, b2.iters, flags=s3a.FLAG_PERSISTENT)
         torch.cuda.synchronize()
-        h.set_tuning(s3a.F32, graph_shape["wg"], graph_shape["items"], graph_shape["occupancy"])
+        if retune:  # the handle keeps one tuned shape per size: the graph path's again
+            h.autotune(pm, b2.tau, b2.delta, b2.iters)
         # bit for bit equal only when both paths use the same tile size
         same = bool(torch.equal(Sp, S)) and bool(torch.equal(ibp, ib))
         # bitwise equal to the checked graph-path result: the oracle verdict carries over
