@@ -338,6 +338,9 @@ def main():
     if "depth" in legs:
         bd = _BATCHES["depth"]
         dm = s3a.DepthPointmaps.from_batch(bd, dev)
+        tune_d = None
+        if not args.no_autotune and not args.tuning:  # depth-map calls keep their own tuned shape
+            tune_d = h.autotune_depth(dm, bd.tau, bd.delta, bd.iters)
         Sd = torch.empty((bd.n_pairs, 16), dtype=torch.float64, device=dev)
         stepd = lambda: h.align_depth_pairs(dm, bd.tau, bd.delta, bd.iters, out=Sd, info=False)
         ms_d = timed(stepd, args.steps, args.warmup)
@@ -350,7 +353,8 @@ def main():
         gbs_d = DEPTH_B_PER_PX * bd.n_points / (kd / kn / 1e3) / 1e9
         ppsd = counted_points(verd, Vd) / (ms_d / 1e3)
         res["depth_fp32"] = dict(ms_per_step=ms_d, points_per_s=ppsd, pixels=bd.n_points, valid_points=Vd,
-                                 kernel_ms=kd, pass_gbs=gbs_d, pass_frac=gbs_d / HBM_PEAK_GBS, verify=verd)
+                                 kernel_ms=kd, pass_gbs=gbs_d, pass_frac=gbs_d / HBM_PEAK_GBS, tuning=tune_d,
+                                 verify=verd)
         log(f"depth fp32: {ms_d:.3f} ms/step, {ppsd / 1e9:.2f} G valid pts/s over {bd.n_points} pixels, "
             f"pass {gbs_d:.0f} GB/s; verify {verd}")
         del dm
@@ -422,6 +426,9 @@ def main():
         b4 = _BATCHES["cfg4"]
         n4 = int(T4.shape[0])
         pm4 = s3a.Pointmaps.from_batch(b4, dev)
+        tune4 = None
+        if not args.no_autotune and not args.tuning:  # its own size class (243 M points)
+            tune4 = h.autotune(pm4, b4.tau, b4.delta, b4.iters)
         S4 = torch.empty((b4.n_pairs, 16), dtype=torch.float64, device=dev)
         st4 = lambda: h.align_pairs(pm4, b4.tau, b4.delta, b4.iters, out=S4, info=False)
         ms_a4 = timed(st4, 5, 1)
@@ -465,6 +472,7 @@ def main():
         res["loop_closure_fp64"] = dict(
             edges=int(len(E4)), nodes=n4, edge_points=b4.n_points, edge_valid_points=V4,
             align_ms=ms_a4, align_points_per_s=counted_points(ver4, V4) / (ms_a4 / 1e3), align_verify=ver4,
+            align_tuning=tune4,
             edges_from_alignment_ms=ms_e4, edge_status_ok=int((est.cpu().numpy() == 0).sum()),
             gn_ms_per_solve=ms_pgo, gn_iters=20, chi2_first=rep.chi2[0], chi2_final=rep.final_chi2,
             status=rep.status, factor_blocks=int(rep.factor_nnz_blocks),

@@ -430,6 +430,11 @@ int s3a_correct_points(s3a_handle* h, int64_t n_corr, const int64_t* src, const 
 /* Time candidate launch shapes on this batch and keep the fastest for its
  * (dtype, size class). Synchronises the stream. best may be NULL. */
 int s3a_autotune(s3a_handle* h, const s3a_align_desc* desc, s3a_tuning* best, s3a_stream stream);
+/* The same for depth-map input: the shape is kept for depth-map calls of this
+ * plane type and size class, apart from stored-point calls (the pass kernels do
+ * different work per byte). Errors as s3a_align_depth_pairs. */
+int s3a_autotune_depth(s3a_handle* h, const s3a_depth_desc* desc, s3a_tuning* best, s3a_stream stream);
+/* Force one shape for every call on planes of dtype, depth-map input included. */
 int s3a_set_tuning(s3a_handle* h, int32_t dtype, const s3a_tuning* t); /* t = NULL: back to automatic */
 int s3a_get_tuning(s3a_handle* h, int32_t dtype, int64_t n_points, s3a_tuning* t);
 

@@ -73,6 +73,7 @@ _EXPORTS = {
     "s3a_pose_graph_solve": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                                             c_void_p, ctypes.POINTER(PgoParams), ctypes.POINTER(PgoReport), c_void_p]),
     "s3a_autotune": (ctypes.c_int, [c_void_p, ctypes.POINTER(AlignDesc), ctypes.POINTER(Tuning), c_void_p]),
+    "s3a_autotune_depth": (ctypes.c_int, [c_void_p, ctypes.POINTER(DepthDesc), ctypes.POINTER(Tuning), c_void_p]),
     "s3a_set_tuning": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.POINTER(Tuning)]),
     "s3a_get_tuning": (ctypes.c_int, [c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.POINTER(Tuning)]),
     "s3a_set_timing": (ctypes.c_int, [c_void_p, ctypes.c_int]),
@@ -395,6 +396,14 @@ class Handle:
         best = Tuning()
         d = pm.desc(tau, delta, iters, flags)
         _check(self.lib.s3a_autotune(self.h, ctypes.byref(d), ctypes.byref(best), _stream(pm.device)), self.h)
+        return dict(wg=best.wg, items=best.items, occupancy=best.occupancy, window=best.window)
+
+    def autotune_depth(self, dm, tau, delta=0.05, iters=10, flags=0):
+        """autotune for depth-map input (DepthPointmaps): the shape is kept for
+        depth-map calls of that plane type and size class."""
+        best = Tuning()
+        d = dm.desc(tau, delta, iters, flags)
+        _check(self.lib.s3a_autotune_depth(self.h, ctypes.byref(d), ctypes.byref(best), _stream(dm.device)), self.h)
         return dict(wg=best.wg, items=best.items, occupancy=best.occupancy, window=best.window)
 
     def set_tuning(self, dtype, wg=None, items=None, occupancy=None, window=0):

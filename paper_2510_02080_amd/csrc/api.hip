@@ -226,18 +226,27 @@ int size_class(int64_t n_points) {
   return c;
 }
 
+// Untuned shapes. Depth-map input does about seven times the arithmetic per
+// byte of stored points and runs best with one workgroup per (longer) tile.
 LaunchCfg default_cfg(int dtype) {
   LaunchCfg c;
   c.wg = 256;
-  c.items = (dtype & 1) ? 2 : 4;
-  c.occupancy = 4;
+  if (dtype == DT_DEPTH_F32 || dtype == DT_DEPTH_BF16) {
+    c.items = 16;
+    c.occupancy = 0;
+  } else {
+    c.items = (dtype & 1) ? 2 : 4;
+    c.occupancy = 4;
+  }
   c.window = 0;
   return c;
 }
 
+// A forced shape applies to plane and depth-map input of its plane type; tuned
+// shapes are kept per input kind (plane or depth map, FP32 or BF16) and size
+// class.
 LaunchCfg pick_cfg(s3a_handle* h, int dtype, int64_t n_points) {
-  dtype &= 1;  // depth inputs use the launch shape of their plane type
-  if (h->forced[dtype]) return h->forced_cfg[dtype];
+  if (h->forced[dtype & 1]) return h->forced_cfg[dtype & 1];
   const int sc = size_class(n_points);
   for (auto& t : h->tuned)
     if (t.dtype == dtype && t.size_class == sc) return t.cfg;
@@ -639,29 +648,39 @@ int s3a_align_pairs(s3a_handle* h, const s3a_align_desc* d, const s3a_sim3* init
   return align_run(h, d, nullptr, init, S_out, info, stream);
 }
 
+}  // extern "C"
+
+// The internal descriptor of a depth-map call (the three planes stand in for
+// the seven, which the descriptor check wants non-null), after checking it.
+static int depth_call_desc(const s3a_depth_desc* dd, s3a_align_desc* d) {
+  if (dd->dtype != S3A_F32 && dd->dtype != S3A_BF16) return S3A_EINVAL;
+  if (dd->flags & S3A_FLAG_PERSISTENT) return S3A_EINVAL;
+  if (dd->n_pairs > 0 && !dd->pairs) return S3A_EINVAL;
+  memset(d, 0, sizeof(*d));
+  d->dtype = dd->dtype == S3A_F32 ? DT_DEPTH_F32 : DT_DEPTH_BF16;
+  d->n_pairs = dd->n_pairs;
+  d->n_points = dd->n_points;
+  d->offsets = dd->offsets;
+  d->px = dd->depth_p; d->py = dd->depth_q; d->pz = dd->conf;
+  d->qx = dd->depth_p; d->qy = dd->depth_q; d->qz = dd->conf; d->conf = dd->conf;
+  d->conf_threshold = dd->conf_threshold;
+  d->irls_iters = dd->irls_iters;
+  d->huber_delta = dd->huber_delta;
+  d->flags = dd->flags;
+  d->reserved = dd->reserved;
+  s3a_align_desc chk = *d;
+  chk.dtype = dd->dtype;
+  return check_desc(&chk);
+}
+
+extern "C" {
+
 int s3a_align_depth_pairs(s3a_handle* h, const s3a_depth_desc* dd, const s3a_sim3* init, s3a_sim3* S_out,
                           s3a_align_info* info, s3a_stream stream) {
   if (!h || !dd) return S3A_EINVAL;
-  if (dd->dtype != S3A_F32 && dd->dtype != S3A_BF16) return S3A_EINVAL;
-  if (dd->flags & S3A_FLAG_PERSISTENT) return S3A_EINVAL;
-  if (dd->n_pairs > 0 && (!S_out || !dd->pairs)) return S3A_EINVAL;
+  if (dd->n_pairs > 0 && !S_out) return S3A_EINVAL;
   s3a_align_desc d;
-  memset(&d, 0, sizeof(d));
-  d.dtype = dd->dtype == S3A_F32 ? DT_DEPTH_F32 : DT_DEPTH_BF16;
-  d.n_pairs = dd->n_pairs;
-  d.n_points = dd->n_points;
-  d.offsets = dd->offsets;
-  // the three depth-input planes; the check below wants seven non-null planes
-  d.px = dd->depth_p; d.py = dd->depth_q; d.pz = dd->conf;
-  d.qx = dd->depth_p; d.qy = dd->depth_q; d.qz = dd->conf; d.conf = dd->conf;
-  d.conf_threshold = dd->conf_threshold;
-  d.irls_iters = dd->irls_iters;
-  d.huber_delta = dd->huber_delta;
-  d.flags = dd->flags;
-  d.reserved = dd->reserved;
-  s3a_align_desc chk = d;
-  chk.dtype = dd->dtype;
-  const int rc = check_desc(&chk);
+  const int rc = depth_call_desc(dd, &d);
   if (rc) return rc;
   if (d.n_pairs == 0) return S3A_OK;
   return align_run(h, &d, dd->pairs, init, S_out, info, stream);
@@ -780,8 +799,8 @@ int s3a_align_pairs_implicit_backward(s3a_handle* h, const s3a_align_desc* d, co
   S3A_TRY(launch_sched(sh, dcd, h->w, st));
   S3A_TRY(launch_prep(sh, dcd, h->w, 0, st));
   TimedLaunch tl(h, st);
-  S3A_TRY(launch_implicit(d->dtype, lc, sh, dcd, h->w, h->hpart, gS, iflags, v_out, status_out, grid_for(h, lc, mt),
-                          st));
+  S3A_TRY(launch_implicit(d->dtype, lc, sh, dcd, h->w, h->hpart, gS, iflags, v_out, status_out, grid_for(h, lc, mt), mt,
+                          h->n_cu, st));
   return S3A_OK;
 }
 
@@ -837,10 +856,13 @@ int s3a_get_tuning(s3a_handle* h, int32_t dtype, int64_t n_points, s3a_tuning* t
   return S3A_OK;
 }
 
-int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_stream stream) {
-  if (!h) return S3A_EINVAL;
-  int rc = check_desc(d);
-  if (rc) return rc;
+}  // extern "C"
+
+// Time the candidate launch shapes on one call (plane or depth-map input; the
+// caller's descriptor is already checked) and keep the fastest for its (input
+// kind, size class).
+static int autotune_run(s3a_handle* h, const s3a_align_desc* d, const s3a_depth_pair* depth, s3a_tuning* best,
+                        s3a_stream stream) {
   if (d->n_pairs == 0) return S3A_OK;
   DeviceGuard g(h->device);
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -851,8 +873,9 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
   hipEvent_t e0, e1;
   (void)hipEventCreate(&e0);
   (void)hipEventCreate(&e1);
-  const bool was_forced = h->forced[d->dtype];
-  const LaunchCfg was_cfg = h->forced_cfg[d->dtype];
+  const int plane = d->dtype & 1;  // the forced shape is per plane type
+  const bool was_forced = h->forced[plane];
+  const LaunchCfg was_cfg = h->forced_cfg[plane];
   LaunchCfg bestc = default_cfg(d->dtype);
   float best_ms = 1e30f;
   const int wgs[2] = {256, 512};
@@ -871,18 +894,18 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
         c.items = it;
         c.occupancy = oc;
         c.window = 0;
-        h->forced[d->dtype] = true;
-        h->forced_cfg[d->dtype] = c;
+        h->forced[plane] = true;
+        h->forced_cfg[plane] = c;
         float ms = 1e30f;
         bool ok = true;
         for (int rep = 0; rep < 4 && ok; ++rep) {
-          if (s3a_align_pairs(h, &dd, nullptr, S, nullptr, stream) != S3A_OK) ok = false;
+          if (align_run(h, &dd, depth, nullptr, S, nullptr, stream) != S3A_OK) ok = false;
           if (rep == 0) {  // warm-up (and graph capture)
             if (hipStreamSynchronize(st) != hipSuccess) ok = false;
             continue;
           }
           (void)hipEventRecord(e0, st);
-          if (s3a_align_pairs(h, &dd, nullptr, S, nullptr, stream) != S3A_OK) ok = false;
+          if (align_run(h, &dd, depth, nullptr, S, nullptr, stream) != S3A_OK) ok = false;
           (void)hipEventRecord(e1, st);
           if (hipEventSynchronize(e1) != hipSuccess) ok = false;
           float t = 0.0f;
@@ -894,8 +917,8 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
           bestc = c;
         }
       }
-  h->forced[d->dtype] = was_forced;
-  h->forced_cfg[d->dtype] = was_cfg;
+  h->forced[plane] = was_forced;
+  h->forced_cfg[plane] = was_cfg;
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   (void)hipFree(S);
@@ -914,6 +937,23 @@ int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_s
     best->window = bestc.window;
   }
   return S3A_OK;
+}
+
+extern "C" {
+
+int s3a_autotune(s3a_handle* h, const s3a_align_desc* d, s3a_tuning* best, s3a_stream stream) {
+  if (!h) return S3A_EINVAL;
+  const int rc = check_desc(d);
+  if (rc) return rc;
+  return autotune_run(h, d, nullptr, best, stream);
+}
+
+int s3a_autotune_depth(s3a_handle* h, const s3a_depth_desc* dd, s3a_tuning* best, s3a_stream stream) {
+  if (!h || !dd) return S3A_EINVAL;
+  s3a_align_desc d;
+  const int rc = depth_call_desc(dd, &d);
+  if (rc) return rc;
+  return autotune_run(h, &d, dd->pairs, best, stream);
 }
 
 int s3a_transform_points(s3a_handle* h, int32_t dtype, int64_t n_points, int32_t n_submaps, const int64_t* offsets,

@@ -37,73 +37,120 @@ __device__ inline void block_store_h(double (&acc)[HSTAT], double (*red)[HSTAT],
   __syncthreads();
 }
 
+// The per-tile pipelined walk over a run of consecutive tiles of one pair, taken
+// as one stream: `items` (even, known only at run time) vectors per lane, lane
+// l's item i at element (i * WG + l) * VEC from the run's first tile. Tiles of
+// a pair lie end to end, so this visits each element of the run once, as the
+// per-tile walks do; the next vector's loads are issued before the current one
+// is worked on.
+template <int WG, int VEC, typename Raw, typename Fetch, typename Body>
+__device__ inline void pipelined_run(int items, int end_rel, Fetch&& fetch, Body&& body) {
+  constexpr int STRIDE = WG * VEC;
+  Raw A, B;
+  const int first = (int)threadIdx.x * VEC;
+  if (first >= end_rel) return;
+  fetch(first, A);
+#pragma unroll 1
+  for (int it = 0; it < items; it += 2) {
+    const int r0 = first + it * STRIDE;
+    const int r1 = r0 + STRIDE;
+    const bool more1 = r1 < end_rel;
+    if (more1) fetch(r1, B);
+    body(A, r0);
+    if (!more1) break;
+    const int r2 = r1 + STRIDE;
+    const bool more2 = it + 2 < items && r2 < end_rel;
+    if (more2) fetch(r2, A);
+    body(B, r1);
+    if (!more2) break;
+  }
+}
+
+// Each workgroup takes a contiguous range of tiles and streams each run of
+// consecutive tiles of one pair as one pipelined sweep: the per-lane sums and
+// the load pipeline carry across the run's tile boundaries, and the 52-value
+// block reduction runs once per run, not once per tile. The run's sums land in
+// the slot of its first tile and its other slots are zeroed, so the finalize
+// (which adds every slot of a pair) is unchanged. The grid changes only the
+// summation order.
 template <int DT, int WG, int ITEMS>
 __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restrict__ cd, Work w, double* hpart) {
   constexpr int VEC = Planes<DT>::VEC;
   __shared__ double red[WG / 64][HSTAT];
   const int total = *w.total_tiles;
+  const int t0 = (int)((int64_t)total * blockIdx.x / gridDim.x);
+  const int t1 = (int)((int64_t)total * (blockIdx.x + 1) / gridDim.x);
   const void* pl[7];
 #pragma unroll
   for (int j = 0; j < 7; ++j) pl[j] = cd->planes[j];
+  const SrcCtx<DT> src{pl};
   const float tau = sh.tau;
   const double delta = sh.delta;
-  for (int t = (int)blockIdx.x; t < total; t += (int)gridDim.x) {
+#pragma unroll 1
+  for (int t = t0; t < t1;) {
     const TileDesc td = load_tile(w.tiles + t);
+    const PairSched sc = w.sched[td.pair];
+    // tiles in this run, capped so that element offsets within it fit an int
+    const int m = min(min(t1, sc.tile0 + sc.ntiles) - t, (int)((1ll << 30) / sh.tile_elems));
+    const int64_t run_end = w.tiles[t + m - 1].end;
     const PointParams P = load_params(w.params + td.pair);
     double a[HSTAT];
 #pragma unroll
     for (int j = 0; j < HSTAT; ++j) a[j] = 0.0;
-    const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(td.end - td.begin);
-    const SrcCtx<DT> src{pl};
-    pipelined_items<WG, ITEMS, VEC, RawVec>(
-        end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(src, td.begin + rel, sh.n_points, r); },
+    const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(run_end - td.begin);
+    pipelined_run<WG, VEC, RawVec>(
+        m * ITEMS, end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(src, td.begin + rel, sh.n_points, r); },
         [&](const RawVec& raw, int rel0) {
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        float x[7];
+          for (int e = 0; e < VEC; ++e) {
+            float x[7];
 #pragma unroll
-        for (int j = 0; j < 7; ++j) x[j] = Planes<DT>::elem(raw, j, e);
-        const bool valid = P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
+            for (int j = 0; j < 7; ++j) x[j] = Planes<DT>::elem(raw, j, e);
+            const bool valid =
+                P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
 #pragma unroll
-        for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;  // masked points add zeros
-        double y[3], r[3];
+            for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;  // masked points add zeros
+            double y[3], r[3];
 #pragma unroll
-        for (int i = 0; i < 3; ++i) {
-          y[i] = fma(P.M[3 * i], (double)x[0], fma(P.M[3 * i + 1], (double)x[1], fma(P.M[3 * i + 2], (double)x[2], P.t[i])));
-          r[i] = y[i] - (double)x[3 + i];
-        }
-        const double c = x[6];
-        const double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-        const double ie = rsqrt(e2);  // 1 / |r|, used only outside delta (|r| > delta > 0)
-        const bool outl = e2 > delta * delta;
-        const double psi = outl ? delta * ie : 1.0;
-        const double om = c * psi;
-        a[0] += om;
+            for (int i = 0; i < 3; ++i) {
+              y[i] = fma(P.M[3 * i], (double)x[0],
+                         fma(P.M[3 * i + 1], (double)x[1], fma(P.M[3 * i + 2], (double)x[2], P.t[i])));
+              r[i] = y[i] - (double)x[3 + i];
+            }
+            const double c = x[6];
+            const double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            const double ie = rsqrt(e2);  // 1 / |r|, used only outside delta (|r| > delta > 0)
+            const bool outl = e2 > delta * delta;
+            const double psi = outl ? delta * ie : 1.0;
+            const double om = c * psi;
+            a[0] += om;
 #pragma unroll
-        for (int i = 0; i < 3; ++i) a[1 + i] = fma(om, y[i], a[1 + i]);
-        a[4] = fma(om * y[0], y[0], a[4]); a[5] = fma(om * y[0], y[1], a[5]); a[6] = fma(om * y[0], y[2], a[6]);
-        a[7] = fma(om * y[1], y[1], a[7]); a[8] = fma(om * y[1], y[2], a[8]); a[9] = fma(om * y[2], y[2], a[9]);
+            for (int i = 0; i < 3; ++i) a[1 + i] = fma(om, y[i], a[1 + i]);
+            a[4] = fma(om * y[0], y[0], a[4]); a[5] = fma(om * y[0], y[1], a[5]); a[6] = fma(om * y[0], y[2], a[6]);
+            a[7] = fma(om * y[1], y[1], a[7]); a[8] = fma(om * y[1], y[2], a[8]); a[9] = fma(om * y[2], y[2], a[9]);
 #pragma unroll
-        for (int i = 0; i < 3; ++i) a[10 + i] = fma(om, r[i], a[10 + i]);
+            for (int i = 0; i < 3; ++i) a[10 + i] = fma(om, r[i], a[10 + i]);
 #pragma unroll
-        for (int i = 0; i < 3; ++i)
+            for (int i = 0; i < 3; ++i)
 #pragma unroll
-          for (int j = 0; j < 3; ++j) a[13 + 3 * i + j] = fma(om * y[i], r[j], a[13 + 3 * i + j]);
-        // rank-one correction of the Huber Hessian outside delta: c psi / e^2 u u^T
-        const double k1 = outl ? om * ie * ie : 0.0;
-        const double u[7] = {r[0], r[1], r[2], y[1] * r[2] - y[2] * r[1], y[2] * r[0] - y[0] * r[2],
-                             y[0] * r[1] - y[1] * r[0], y[0] * r[0] + y[1] * r[1] + y[2] * r[2]};
+              for (int j = 0; j < 3; ++j) a[13 + 3 * i + j] = fma(om * y[i], r[j], a[13 + 3 * i + j]);
+            // rank-one correction of the Huber Hessian outside delta: c psi / e^2 u u^T
+            const double k1 = outl ? om * ie * ie : 0.0;
+            const double u[7] = {r[0], r[1], r[2], y[1] * r[2] - y[2] * r[1], y[2] * r[0] - y[0] * r[2],
+                                 y[0] * r[1] - y[1] * r[0], y[0] * r[0] + y[1] * r[1] + y[2] * r[2]};
 #pragma unroll
-        for (int i = 0; i < 7; ++i) {
-          const double ku = k1 * u[i];
+            for (int i = 0; i < 7; ++i) {
+              const double ku = k1 * u[i];
 #pragma unroll
-          for (int j = 0; j <= i; ++j) a[22 + i * (i + 1) / 2 + j] = fma(ku, u[j], a[22 + i * (i + 1) / 2 + j]);
-        }
-        a[50] += c;
-        a[51] += valid ? 1.0 : 0.0;
-      }
-    });
+              for (int j = 0; j <= i; ++j) a[22 + i * (i + 1) / 2 + j] = fma(ku, u[j], a[22 + i * (i + 1) / 2 + j]);
+            }
+            a[50] += c;
+            a[51] += valid ? 1.0 : 0.0;
+          }
+        });
     block_store_h<WG>(a, red, hpart + (int64_t)t * HSTAT);
+    for (int i = (int)threadIdx.x; i < (m - 1) * HSTAT; i += WG) hpart[(int64_t)(t + 1) * HSTAT + i] = 0.0;
+    t += m;
   }
 }
 
@@ -305,15 +352,25 @@ __global__ __launch_bounds__(WG) void k_igrad(Shape sh, const CallDesc* __restri
   }
 }
 
+// Workgroups of a kernel that one compute unit holds at once (at least 1).
+template <typename K>
+static int resident_per_cu(K kernel, int wg) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, wg, 0) != hipSuccess) n = 1;
+  return std::max(n, 1);
+}
+
 template <int DT>
 static hipError_t launch_implicit_t(const LaunchCfg& lc, const Shape& sh, const CallDesc* cd, const Work& w,
                                     double* hpart, const double* gS, uint32_t iflags, double* v_out, int32_t* status_out,
-                                    int grid, hipStream_t st) {
+                                    int grid, int64_t max_tiles, int n_cu, hipStream_t st) {
 #define S3A_CASE(WGV, IT)                                                                                   \
   if (lc.wg == WGV && lc.items == IT) {                                                                     \
-    hipLaunchKernelGGL((k_hess<DT, WGV, IT>), dim3(grid), dim3(WGV), 0, st, sh, cd, w, hpart);             \
-    hipError_t e = hipGetLastError();                                                                       \
-    if (e != hipSuccess) return e;                                                                          \
+    static const int per_cu = resident_per_cu(k_hess<DT, WGV, IT>, WGV);                                  \
+    const int64_t hgrid = std::max<int64_t>(1, std::min<int64_t>(max_tiles, (int64_t)per_cu * n_cu));      \
+    hipError_t e;                                                                                           \
+    hipLaunchKernelGGL((k_hess<DT, WGV, IT>), dim3(hgrid), dim3(WGV), 0, st, sh, cd, w, hpart);            \
+    if ((e = hipGetLastError()) != hipSuccess) return e;                                                    \
     hipLaunchKernelGGL(k_finalize_implicit, dim3(sh.n_pairs), dim3(64), 0, st, sh, cd, w, hpart, gS, iflags, \
                        v_out, status_out);                                                                  \
     if ((e = hipGetLastError()) != hipSuccess) return e;                                                    \
@@ -328,10 +385,11 @@ static hipError_t launch_implicit_t(const LaunchCfg& lc, const Shape& sh, const 
 
 hipError_t launch_implicit(int dtype, const LaunchCfg& lc, const Shape& sh, const CallDesc* cd, const Work& w,
                            double* hpart, const double* gS, uint32_t iflags, double* v_out, int32_t* status_out,
-                           int grid, hipStream_t st) {
+                           int grid, int64_t max_tiles, int n_cu, hipStream_t st) {
   if (sh.n_pairs == 0) return hipSuccess;
-  return dtype == S3A_F32 ? launch_implicit_t<S3A_F32>(lc, sh, cd, w, hpart, gS, iflags, v_out, status_out, grid, st)
-                          : launch_implicit_t<S3A_BF16>(lc, sh, cd, w, hpart, gS, iflags, v_out, status_out, grid, st);
+  return dtype == S3A_F32
+             ? launch_implicit_t<S3A_F32>(lc, sh, cd, w, hpart, gS, iflags, v_out, status_out, grid, max_tiles, n_cu, st)
+             : launch_implicit_t<S3A_BF16>(lc, sh, cd, w, hpart, gS, iflags, v_out, status_out, grid, max_tiles, n_cu, st);
 }
 
 }  // namespace s3a

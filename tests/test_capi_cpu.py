@@ -87,6 +87,8 @@ def test_host_argument_checks(lib):
     assert L.s3a_destroy(None) == b.EINVAL
     assert L.s3a_set_tuning(None, 0, None) == b.EINVAL
     assert L.s3a_align_depth_pairs(None, None, None, None, None, None) == b.EINVAL
+    assert L.s3a_autotune(None, ctypes.byref(d), None, None) == b.EINVAL
+    assert L.s3a_autotune_depth(None, None, None, None) == b.EINVAL
     assert L.s3a_align_pairs_implicit_backward(None, ctypes.byref(d), None, None, 0, *([None] * 9), None) == b.EINVAL
     assert L.s3a_transform_points(None, 0, 0, 0, None, *([None] * 8), None) == b.EINVAL
     assert L.s3a_correct_points(None, 0, None, None, 0, None, None, None, 0, None, None, None, None, None) == b.EINVAL

@@ -94,3 +94,28 @@ def test_depth_workload_sampled(h):
     rng = np.random.default_rng(42)
     for k in sorted(set([0, b.n_pairs - 1] + list(rng.choice(b.n_pairs, 3, replace=False)))):
         check_pair(T[k], info[k], oracle_pair(b, int(k)), where=f"depth pair {k}", dr=DR_DEPTH)
+
+
+def test_autotune_depth_keeps_its_own_shape(h):
+    """s3a_autotune_depth picks a shape for depth-map calls of its size class
+    and leaves the stored-point tuning alone; the tuned call matches the
+    oracle and equals a forced run at the shape it picked, bit for bit."""
+    b = small_batch()
+    dm = s3a.DepthPointmaps.from_batch(b, "cuda:0")
+    h2 = s3a.Handle(0)
+    before = h2.get_tuning(s3a.F32, b.n_points)
+    best = h2.autotune_depth(dm, b.tau, b.delta, b.iters)
+    assert best["wg"] in (256, 512) and best["items"] in (2, 4, 8, 16)
+    assert h2.get_tuning(s3a.F32, b.n_points) == before
+    S, ib = h2.align_depth_pairs(dm, b.tau, b.delta, b.iters)
+    h2.set_tuning(s3a.F32, best["wg"], best["items"], best["occupancy"])
+    Sf, ibf = h2.align_depth_pairs(dm, b.tau, b.delta, b.iters)
+    torch.cuda.synchronize()
+    assert torch.equal(S, Sf) and torch.equal(ib, ibf)
+    T, info = s3a.sim3_to_numpy(S), s3a.info_to_numpy(ib)
+    for k in range(b.n_pairs):
+        ref = oracle_pair(b, k)
+        if ref is None:
+            assert int(info[k]["status"]) == s3a.PAIR_BADRANGE, k
+            continue
+        check_pair(T[k], info[k], ref, where=f"tuned pair {k}", dr=DR_DEPTH)
