@@ -61,8 +61,8 @@ struct s3a_handle {
   bool timing = false;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_used, ev_free;
   int32_t* flags_dev = nullptr;  // small device scratch (offset-check flag of the point transform)
-  double* hpart = nullptr;       // per-tile sums of the implicit-derivative pass
-  int64_t hpart_tiles = 0;
+  double* hpart = nullptr;       // per-run sums of the implicit-derivative pass
+  int64_t hpart_tiles = 0;       // slots of 52 doubles
   // issue order of calls across streams (they share the workspace)
   hipEvent_t order_ev = nullptr;
   hipStream_t order_stream = nullptr;
@@ -780,15 +780,16 @@ int s3a_align_pairs_implicit_backward(s3a_handle* h, const s3a_align_desc* d, co
   if (mt >= (1ll << 31)) return S3A_EINVAL;
   rc = ensure_workspace(h, d->n_pairs, mt);
   if (rc) return rc;
-  if (h->hpart_tiles < mt) {
+  const int64_t hslots = mt + d->n_pairs;  // the Hessian pass's slots: at most one per workgroup and pair run
+  if (h->hpart_tiles < hslots) {
     if (h->hpart) {
       S3A_TRY(hipStreamSynchronize(st));
       (void)hipFree(h->hpart);
       h->hpart = nullptr;
       h->hpart_tiles = 0;
     }
-    S3A_TRY(hipMalloc(&h->hpart, sizeof(double) * 52 * (size_t)mt));
-    h->hpart_tiles = mt;
+    S3A_TRY(hipMalloc(&h->hpart, sizeof(double) * 52 * (size_t)hslots));
+    h->hpart_tiles = hslots;
   }
   CallDesc c = make_call(d);
   c.S_in = S;

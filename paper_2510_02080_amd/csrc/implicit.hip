@@ -10,32 +10,133 @@
 
 namespace s3a {
 
-// Per-tile sums of the Hessian pass (weights om = c psi, c-weighted; divided
-// by C = sum m c in the finalize). y = S* p, r = y - q, all in FP64:
+// Sums of the Hessian pass, per run of a workgroup's rows within one pair
+// (weights om = c psi, c-weighted; divided by C = sum m c in the finalize).
+// y = S* p, r = y - q, all in FP64 (the rank-one sums in FP32, see below):
 //   0 sum om, 1-3 sum om y, 4-9 sum om y y^T (xx xy xz yy yz zz),
 //   10-12 sum om r, 13-21 sum om y_a r_b (row-major a, b),
 //   22-49 sum over points outside delta of c psi / e^2 u u^T, u = (r, y x r, y . r)
 //         (packed lower triangle, row i at i (i + 1) / 2),
-//   50 C, 51 valid count.
+//   50 C, 51 unused (zero; 52 values halve evenly in the reduction).
 constexpr int HSTAT = 52;
 
+// One FP64 value's two halves through a lane-swap builtin pair.
+template <bool HALF16>
+__device__ inline void swap_f64(double& x, double& y) {
+  const unsigned long long a = (unsigned long long)__double_as_longlong(x);
+  const unsigned long long b = (unsigned long long)__double_as_longlong(y);
+  unsigned alo = (unsigned)a, ahi = (unsigned)(a >> 32), blo = (unsigned)b, bhi = (unsigned)(b >> 32);
+  if constexpr (HALF16) {
+    const auto l = __builtin_amdgcn_permlane16_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(ahi, bhi, false, false);
+    alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
+  } else {
+    const auto l = __builtin_amdgcn_permlane32_swap(alo, blo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(ahi, bhi, false, false);
+    alo = l[0]; blo = l[1]; ahi = h[0]; bhi = h[1];
+  }
+  x = __longlong_as_double((long long)(((unsigned long long)ahi << 32) | alo));
+  y = __longlong_as_double((long long)(((unsigned long long)bhi << 32) | blo));
+}
+
+// Sums of the HSTAT per-lane values over the workgroup, stored to out. Within
+// a wavefront the values are halved twice by lane swaps: swapping lanes 32-63
+// of value j with lanes 0-31 of value j + 26 and adding leaves lanes 0-31 with
+// value j and lanes 32-63 with value j + 26, each summed over two lanes; the
+// same with 16-lane swaps within each half leaves lane l with values
+// 13 (l / 16) + s, s < 13, summed over four lanes. A butterfly over each row of
+// 16 lanes finishes them (about a third of the instructions of reducing all 52
+// values over 64 lanes), then one lane per row stores its 13 totals to LDS.
 template <int WG>
 __device__ inline void block_store_h(double (&acc)[HSTAT], double (*red)[HSTAT], double* out) {
+  static_assert(HSTAT == 52, "the lane halving takes 52 values");
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  wave_totals_f64(acc);
-  if (lane == 0) {
+  double z[26];
 #pragma unroll
-    for (int j = 0; j < HSTAT; ++j) red[wv][j] = acc[j];
+  for (int j = 0; j < 26; ++j) {
+    double x = acc[j], y = acc[j + 26];
+    swap_f64<false>(x, y);
+    z[j] = x + y;
+  }
+  double q[13];
+#pragma unroll
+  for (int j = 0; j < 13; ++j) {
+    double x = z[j], y = z[j + 13];
+    swap_f64<true>(x, y);
+    q[j] = x + y;
+  }
+#pragma unroll
+  for (int j = 0; j < 13; ++j) q[j] += dpp_f64<0xb1, 0xf>(q[j]);   // quad_perm [1,0,3,2]
+#pragma unroll
+  for (int j = 0; j < 13; ++j) q[j] += dpp_f64<0x4e, 0xf>(q[j]);   // quad_perm [2,3,0,1]
+#pragma unroll
+  for (int j = 0; j < 13; ++j) q[j] += dpp_f64<0x141, 0xf>(q[j]);  // row_half_mirror
+#pragma unroll
+  for (int j = 0; j < 13; ++j) q[j] += dpp_f64<0x140, 0xf>(q[j]);  // row_mirror
+  if ((lane & 15) == 0) {
+#pragma unroll
+    for (int j = 0; j < 13; ++j) red[wv][13 * (lane >> 4) + j] = q[j];
   }
   __syncthreads();
   if ((int)threadIdx.x < HSTAT) {
     double s = 0.0;
 #pragma unroll
-    for (int q = 0; q < WG / 64; ++q) s += red[q][threadIdx.x];
+    for (int w4 = 0; w4 < WG / 64; ++w4) s += red[w4][threadIdx.x];
     out[threadIdx.x] = s;
   }
   __syncthreads();
 }
+
+// The Hessian pass reads 8-byte vectors per plane (2 FP32 or 4 BF16 points):
+// its FP64 sums need 104 registers per lane, and half-width raw buffers and
+// fewer points in flight per lane let more wavefronts share a SIMD.
+typedef unsigned int s3a_u2 __attribute__((ext_vector_type(2)));
+template <int DT>
+struct HalfVec;
+template <>
+struct HalfVec<S3A_F32> {
+  static constexpr int VEC = 2;
+  typedef s3a_u2 Raw[7];
+  __device__ static inline void fetch(const SrcCtx<S3A_F32>& src, int64_t g0, int64_t n, Raw& r) {
+    if (g0 + 2 <= n) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u2*)(static_cast<const uint32_t*>(src.pl[j]) + g0));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+#pragma unroll
+        for (int e = 0; e < 2; ++e) r[j][e] = (g0 + e < n) ? static_cast<const uint32_t*>(src.pl[j])[g0 + e] : 0u;
+    }
+  }
+  __device__ static inline float elem(const Raw& r, int j, int e) { return __uint_as_float(r[j][e]); }
+};
+template <>
+struct HalfVec<S3A_BF16> {
+  static constexpr int VEC = 4;
+  typedef s3a_u2 Raw[7];
+  __device__ static inline void fetch(const SrcCtx<S3A_BF16>& src, int64_t g0, int64_t n, Raw& r) {
+    if (g0 + 4 <= n) {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+        r[j] = __builtin_nontemporal_load((const S3A_GLOBAL s3a_u2*)(static_cast<const uint16_t*>(src.pl[j]) + g0));
+    } else {
+#pragma unroll
+      for (int j = 0; j < 7; ++j)
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const uint16_t* hp = static_cast<const uint16_t*>(src.pl[j]);
+          const uint32_t a = (g0 + 2 * i < n) ? hp[g0 + 2 * i] : 0u;
+          const uint32_t b = (g0 + 2 * i + 1 < n) ? hp[g0 + 2 * i + 1] : 0u;
+          r[j][i] = a | (b << 16);
+        }
+    }
+  }
+  __device__ static inline float elem(const Raw& r, int j, int e) {
+    const uint32_t u = r[j][e >> 1];
+    return __uint_as_float((e & 1) ? (u & 0xffff0000u) : (u << 16));
+  }
+};
 
 // The per-tile pipelined walk over a run of consecutive tiles of one pair, taken
 // as one stream: `items` (even, known only at run time) vectors per lane, lane
@@ -66,20 +167,34 @@ __device__ inline void pipelined_run(int items, int end_rel, Fetch&& fetch, Body
   }
 }
 
-// Each workgroup takes a contiguous range of tiles and streams each run of
-// consecutive tiles of one pair as one pipelined sweep: the per-lane sums and
-// the load pipeline carry across the run's tile boundaries, and the 52-value
-// block reduction runs once per run, not once per tile. The run's sums land in
-// the slot of its first tile and its other slots are zeroed, so the finalize
-// (which adds every slot of a pair) is unchanged. The grid changes only the
-// summation order.
+// Rows of the Hessian pass: a tile of the call holds HessRows<DT, ITEMS> rows
+// of WG x HalfVec<DT>::VEC elements; global row r of tile t is r - t * RPT of
+// that tile. Workgroup g of G sweeps the rows [R g / G, R (g + 1) / G) of the
+// R = tiles x RPT rows, so every workgroup has the same share up to one row.
+template <int DT, int ITEMS>
+struct HessRows {
+  static constexpr int RPT = ITEMS * Planes<DT>::VEC / HalfVec<DT>::VEC;
+};
+
+// The workgroup whose rows hold global row r.
+__host__ __device__ inline int hess_wg_of_row(int64_t r, int64_t R, int G) { return (int)(((r + 1) * G - 1) / R); }
+
+// Each workgroup streams each run of its rows that belongs to one pair as one
+// pipelined sweep (rows of consecutive tiles lie end to end) and reduces its
+// per-lane sums once per run, into slot g + k for workgroup g and pair k (the
+// runs are ordered by workgroup and pair, so the slots are distinct; the
+// finalize adds the slots of the workgroups that cover the pair's rows). The
+// grid changes only the summation order.
 template <int DT, int WG, int ITEMS>
 __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restrict__ cd, Work w, double* hpart) {
-  constexpr int VEC = Planes<DT>::VEC;
+  using HV = HalfVec<DT>;
+  constexpr int VEC = HV::VEC;
+  constexpr int RPT = HessRows<DT, ITEMS>::RPT;
+  constexpr int STRIDE = WG * VEC;
   __shared__ double red[WG / 64][HSTAT];
-  const int total = *w.total_tiles;
-  const int t0 = (int)((int64_t)total * blockIdx.x / gridDim.x);
-  const int t1 = (int)((int64_t)total * (blockIdx.x + 1) / gridDim.x);
+  const int64_t R = (int64_t)(*w.total_tiles) * RPT;
+  const int G = (int)gridDim.x, g = (int)blockIdx.x;
+  const int64_t r0 = R * g / G, r1 = R * (g + 1) / G;
   const void* pl[7];
 #pragma unroll
   for (int j = 0; j < 7; ++j) pl[j] = cd->planes[j];
@@ -87,25 +202,31 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
   const float tau = sh.tau;
   const double delta = sh.delta;
 #pragma unroll 1
-  for (int t = t0; t < t1;) {
+  for (int64_t row = r0; row < r1;) {
+    const int t = (int)(row / RPT);
     const TileDesc td = load_tile(w.tiles + t);
     const PairSched sc = w.sched[td.pair];
-    // tiles in this run, capped so that element offsets within it fit an int
-    const int m = min(min(t1, sc.tile0 + sc.ntiles) - t, (int)((1ll << 30) / sh.tile_elems));
-    const int64_t run_end = w.tiles[t + m - 1].end;
+    const int64_t re = min(r1, (int64_t)(sc.tile0 + sc.ntiles) * RPT);  // this run: rows [row, re)
+    const int64_t base = td.begin + (row - (int64_t)t * RPT) * STRIDE;   // element of the run's first row
+    const int64_t stop = min(w.tiles[(re - 1) / RPT].end, base + (re - row) * STRIDE);
     const PointParams P = load_params(w.params + td.pair);
     double a[HSTAT];
 #pragma unroll
     for (int j = 0; j < HSTAT; ++j) a[j] = 0.0;
-    const int lo_rel = (int)(td.lo - td.begin), end_rel = (int)(run_end - td.begin);
-    pipelined_run<WG, VEC, RawVec>(
-        m * ITEMS, end_rel, [&](int rel, RawVec& r) { Planes<DT>::fetch(src, td.begin + rel, sh.n_points, r); },
-        [&](const RawVec& raw, int rel0) {
+    float b[28];  // the rank-one sums (22-49), per lane in FP32
+#pragma unroll
+    for (int j = 0; j < 28; ++j) b[j] = 0.0f;
+    const int64_t lo64 = td.lo - base;
+    const int lo_rel = lo64 < 0 ? 0 : (int)lo64;
+    const int end_rel = (int)(stop > base ? stop - base : 0);
+    pipelined_run<WG, VEC, typename HV::Raw>(
+        (int)(re - row), end_rel, [&](int rel, typename HV::Raw& q) { HV::fetch(src, base + rel, sh.n_points, q); },
+        [&](const typename HV::Raw& raw, int rel0) {
 #pragma unroll
           for (int e = 0; e < VEC; ++e) {
             float x[7];
 #pragma unroll
-            for (int j = 0; j < 7; ++j) x[j] = Planes<DT>::elem(raw, j, e);
+            for (int j = 0; j < 7; ++j) x[j] = HV::elem(raw, j, e);
             const bool valid =
                 P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
 #pragma unroll
@@ -119,7 +240,10 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
             }
             const double c = x[6];
             const double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
-            const double ie = rsqrt(e2);  // 1 / |r|, used only outside delta (|r| > delta > 0)
+            // 1 / |r|, used only outside delta (|r| > delta > 0): the hardware
+            // estimate and one Newton step (relative error near 1e-14)
+            double ie = __builtin_amdgcn_rsq(e2);
+            ie = ie * fma(-0.5 * e2 * ie, ie, 1.5);
             const bool outl = e2 > delta * delta;
             const double psi = outl ? delta * ie : 1.0;
             const double om = c * psi;
@@ -134,23 +258,28 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
             for (int i = 0; i < 3; ++i)
 #pragma unroll
               for (int j = 0; j < 3; ++j) a[13 + 3 * i + j] = fma(om * y[i], r[j], a[13 + 3 * i + j]);
-            // rank-one correction of the Huber Hessian outside delta: c psi / e^2 u u^T
-            const double k1 = outl ? om * ie * ie : 0.0;
-            const double u[7] = {r[0], r[1], r[2], y[1] * r[2] - y[2] * r[1], y[2] * r[0] - y[0] * r[2],
-                                 y[0] * r[1] - y[1] * r[0], y[0] * r[0] + y[1] * r[1] + y[2] * r[2]};
+            // rank-one correction of the Huber Hessian outside delta: c psi / e^2 u u^T,
+            // in FP32: it is the Hessian of the few down-weighted points (psi =
+            // delta / |r| < 1), a small share of H, so FP32 products and per-lane
+            // sums leave H's relative error near 1e-9
+            const float k1 = outl ? (float)(om * ie * ie) : 0.0f;
+            const float yf[3] = {(float)y[0], (float)y[1], (float)y[2]};
+            const float rf[3] = {(float)r[0], (float)r[1], (float)r[2]};
+            const float u[7] = {rf[0], rf[1], rf[2], yf[1] * rf[2] - yf[2] * rf[1], yf[2] * rf[0] - yf[0] * rf[2],
+                                yf[0] * rf[1] - yf[1] * rf[0], yf[0] * rf[0] + yf[1] * rf[1] + yf[2] * rf[2]};
 #pragma unroll
             for (int i = 0; i < 7; ++i) {
-              const double ku = k1 * u[i];
+              const float ku = k1 * u[i];
 #pragma unroll
-              for (int j = 0; j <= i; ++j) a[22 + i * (i + 1) / 2 + j] = fma(ku, u[j], a[22 + i * (i + 1) / 2 + j]);
+              for (int j = 0; j <= i; ++j) b[i * (i + 1) / 2 + j] = fmaf(ku, u[j], b[i * (i + 1) / 2 + j]);
             }
             a[50] += c;
-            a[51] += valid ? 1.0 : 0.0;
           }
         });
-    block_store_h<WG>(a, red, hpart + (int64_t)t * HSTAT);
-    for (int i = (int)threadIdx.x; i < (m - 1) * HSTAT; i += WG) hpart[(int64_t)(t + 1) * HSTAT + i] = 0.0;
-    t += m;
+#pragma unroll
+    for (int j = 0; j < 28; ++j) a[22 + j] = (double)b[j];
+    block_store_h<WG>(a, red, hpart + (int64_t)(g + td.pair) * HSTAT);
+    row = re;
   }
 }
 
@@ -158,8 +287,9 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
 // v = H^{-1} g_S; published for the gradient pass (state: g = v, cost_lin =
 // v^T F, C; params: active).
 __global__ __launch_bounds__(64) void k_finalize_implicit(Shape sh, const CallDesc* __restrict__ cd, Work w,
-                                                          const double* __restrict__ hpart, const double* __restrict__ gS,
-                                                          uint32_t iflags, double* v_out, int32_t* status_out) {
+                                                          const double* __restrict__ hpart, int rpt, int hess_grid,
+                                                          const double* __restrict__ gS, uint32_t iflags, double* v_out,
+                                                          int32_t* status_out) {
   const int k = blockIdx.x;
   if (k >= sh.n_pairs) return;
   const PairSched sc = w.sched[k];
@@ -167,8 +297,12 @@ __global__ __launch_bounds__(64) void k_finalize_implicit(Shape sh, const CallDe
   double s[HSTAT];
 #pragma unroll
   for (int j = 0; j < HSTAT; ++j) s[j] = 0.0;
-  for (int t = sc.tile0 + lane; t < sc.tile0 + sc.ntiles; t += 64) {
-    const double* p = hpart + (int64_t)t * HSTAT;
+  const int64_t R = (int64_t)(*w.total_tiles) * rpt;
+  const int g_lo = hess_wg_of_row((int64_t)sc.tile0 * rpt, R, hess_grid);
+  const int g_hi = hess_wg_of_row((int64_t)(sc.tile0 + sc.ntiles) * rpt - 1, R, hess_grid);
+  for (int g = g_lo + lane; g <= g_hi; g += 64) {
+    if (R * (g + 1) / hess_grid == R * g / hess_grid) continue;  // a workgroup with no rows wrote no slot
+    const double* p = hpart + (int64_t)(g + k) * HSTAT;
 #pragma unroll
     for (int j = 0; j < HSTAT; ++j) s[j] += p[j];
   }
@@ -371,8 +505,8 @@ static hipError_t launch_implicit_t(const LaunchCfg& lc, const Shape& sh, const 
     hipError_t e;                                                                                           \
     hipLaunchKernelGGL((k_hess<DT, WGV, IT>), dim3(hgrid), dim3(WGV), 0, st, sh, cd, w, hpart);            \
     if ((e = hipGetLastError()) != hipSuccess) return e;                                                    \
-    hipLaunchKernelGGL(k_finalize_implicit, dim3(sh.n_pairs), dim3(64), 0, st, sh, cd, w, hpart, gS, iflags, \
-                       v_out, status_out);                                                                  \
+    hipLaunchKernelGGL(k_finalize_implicit, dim3(sh.n_pairs), dim3(64), 0, st, sh, cd, w, hpart,            \
+                       HessRows<DT, IT>::RPT, (int)hgrid, gS, iflags, v_out, status_out);                   \
     if ((e = hipGetLastError()) != hipSuccess) return e;                                                    \
     hipLaunchKernelGGL((k_igrad<DT, WGV, IT>), dim3(grid), dim3(WGV), 0, st, sh, cd, w);                   \
     return hipGetLastError();                                                                               \
