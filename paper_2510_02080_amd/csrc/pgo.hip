@@ -75,6 +75,7 @@ struct PgoDev {
   const int32_t* dt_tgt; const int32_t* dt_ptr; const int32_t* dup_a; const int32_t* dup_b;
   double* F;
   double* Finv;
+  double* Frd;    // [nF] 1 / L_jj of the front's factor
   // rows of L: blocks (c, k), k < c (the clique rows' right-hand side)
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
@@ -283,17 +284,15 @@ __device__ inline double wg_sum(double v, double* sh) {
 }
 
 // Dense front of the trailing clique: at most PGO_KMAX node columns; panels of FB
-// columns, trailing updates in FT x FT tiles, one workgroup of FRONT_WG threads.
+// columns, trailing updates in FT x FT tiles.
 constexpr int PGO_KMAX = 72;
 constexpr int FB = 32;
 constexpr int FT = 64;
 constexpr int FRONT_MAX = 512;
-constexpr int FRONT_WG = 512;
 typedef double d4 __attribute__((ext_vector_type(4)));
 static_assert((7 * PGO_KMAX + FT - 1) / FT * FT <= FRONT_MAX, "front order");
 constexpr int FIN_WG = 512;  // solves: 256 registers per lane
 static_assert(FIN_WG % FB == 0 && (FIN_WG / FB) <= 64 && ((FIN_WG / FB) & (FIN_WG / FB - 1)) == 0, "row slots per front column");
-static_assert(FRONT_MAX - FB <= FRONT_WG, "one panel row per thread");
 
 // Element `lane` of factor block `target` (diagonal c, or m + off-diagonal block).
 __device__ inline double* target_elem(const PgoDev& d, int target, int lane) {
@@ -559,24 +558,31 @@ __device__ inline double readlane_f64(double x, int l) {
   return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// LDS of the front's diagonal-block step (file scope, so that its addresses are
-// constants for the non-inlined function that uses them).
-__shared__ double front_Vs[FB * FB];         // inverse of the panel's diagonal factor, row-major
-__shared__ double front_LsT[FB * (FB + 1)];  // the diagonal factor by column
-__shared__ double front_cb[2 * (FB + 1)];    // columns being broadcast
+// LDS of the diagonal-block factor: columns being broadcast (two buffers used in turn).
+__shared__ double front_cb[2 * (FB + 1)];
 
-// (1) of the front factorisation for the diagonal block at (kd, kd), by one
-// wavefront. The factor: lane = row, right-looking; the pivot is read from its
-// lane, and each updated column is written to LDS (cb, two buffers used in turn)
-// one step before it is needed. The factor goes back to F and, by column, to
-// front_LsT. Its inverse: lane = column, right-looking forward substitution
-// against e_lane, to front_Vs and Vg, row-major. Lanes exchange values through
-// LDS with a wavefront fence between writes and reads. False (in every lane) if a
-// pivot is not positive.
-__device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, double* Vg) {
+// Right-looking blocked Cholesky of the front F (order nF, a multiple of FT;
+// column-major, lower triangle) in place, panel by panel of FB columns, one
+// launch per panel across the chip (the diagonal blocks stay a chain: each
+// panel needs the previous one's update):
+//   k_front_diag    the first diagonal block (one wavefront, front_factor);
+//   k_front_update  panel k0, whose diagonal block is factored: one workgroup per
+//                   FT x FT tile of the trailing lower triangle solves the panel
+//                   rows it needs and updates its tile on the matrix cores; the
+//                   workgroup of the leading tile then factors the next diagonal
+//                   block, and one more workgroup inverts panel k0's diagonal
+//                   block for the solves (front_inverse), off the chain;
+//   k_front_inverse the last diagonal block's inverse.
+// Only the factor of each diagonal block is on the chain: pivots by reciprocal
+// square root (hardware estimate, two Newton steps), no division, no inverse.
+constexpr int FRONT_TWG = 256;
+
+// (1) on the chain: the FB x FB diagonal block at (kd, kd) factored in place by
+// one wavefront (lane = row, right-looking: the pivot is read from its lane,
+// each updated column goes to LDS one step before it is needed); 1 / L_jj to
+// rd. False (in every lane) if a pivot is not positive.
+__device__ __attribute__((always_inline)) inline bool front_factor(double* F, int n, int kd, int lane, double* rd) {
   double* cb = front_cb;
-  double* LsT = front_LsT;
-  double* Vs = front_Vs;
   const int r = lane < FB ? lane : FB - 1, e = lane < FB ? lane : FB;
   double a[FB];  // row r; entries above the diagonal carry values that are never read
 #pragma unroll
@@ -591,10 +597,13 @@ __device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, doub
     double* nxt = cb + ((k + 1) & 1) * (FB + 1);
     const double dkk = readlane_f64(a[k], k);
     ok = ok && dkk > 0.0;
-    const double lkk = sqrt(dkk > 0.0 ? dkk : 1.0), rk = 1.0 / lkk;
+    const double x = dkk > 0.0 ? dkk : 1.0;
+    double rk = __builtin_amdgcn_rsq(x);
+    rk = rk * fma(-0.5 * x * rk, rk, 1.5);
+    rk = rk * fma(-0.5 * x * rk, rk, 1.5);
+    const double lkk = x * rk;
     a[k] = lane == k ? lkk : a[k] * rk;
     rv = lane == k ? rk : rv;
-    LsT[k * (FB + 1) + e] = a[k];
     const double m = a[k] * rk;  // L_rk / L_kk, and L_jk = cur[j] / L_kk
     if (k + 1 < FB) {
       a[k + 1] -= m * cur[k + 1];
@@ -608,145 +617,162 @@ __device__ __noinline__ bool front_diag(double* F, int n, int kd, int lane, doub
 #pragma unroll
     for (int c = 0; c < FB; ++c)
       if (c <= lane) F[(size_t)(kd + c) * n + kd + lane] = a[c];
+    rd[lane] = rv;
   }
-  wave_sync();
-  cb[e] = rv;
+  return ok;
+}
+
+// The inverse V = L_kk^{-1} of a factored diagonal block (row-major, to Vg), by
+// one wavefront: lane = column, forward substitution against e_lane.
+__device__ __noinline__ void front_inverse(const double* F, int n, int kd, int lane, const double* rd, double* Vg,
+                                     double* Ls) {
+  for (int x = lane; x < FB * FB; x += 64) {
+    const int c = x / FB, i = x % FB;  // L(i, c) by column
+    Ls[c * (FB + 1) + i] = i >= c ? F[(size_t)(kd + c) * n + kd + i] : 0.0;
+  }
   wave_sync();
   double t[FB];
 #pragma unroll
   for (int i = 0; i < FB; ++i) t[i] = i == lane ? 1.0 : 0.0;
 #pragma unroll
   for (int k = 0; k < FB; ++k) {
-    const double v = t[k] * cb[k];
+    const double v = t[k] * rd[k];
     t[k] = v;
 #pragma unroll
-    for (int i = k + 1; i < FB; ++i) t[i] -= LsT[k * (FB + 1) + i] * v;
+    for (int i = k + 1; i < FB; ++i) t[i] -= Ls[k * (FB + 1) + i] * v;
   }
   if (lane < FB) {
 #pragma unroll
-    for (int i = 0; i < FB; ++i) {
-      Vs[i * FB + lane] = t[i];
-      Vg[i * FB + lane] = t[i];
-    }
+    for (int i = 0; i < FB; ++i) Vg[i * FB + lane] = t[i];
   }
-  return ok;
 }
 
-// Right-looking blocked Cholesky of the front F (order nF, column-major, lower
-// triangle) in place, by one workgroup, panel by panel of FB columns:
-//  (1) the FB x FB diagonal block and its inverse by one wavefront (front_diag);
-//      the inverse goes to LDS (for (2)) and to Finv (for the solves);
-//  (2) the rows below: L_i = A_i L_kk^{-T} = A_i (L_kk^{-1})^T on the FP64 matrix
-//      cores, one wavefront per 16 rows, written to F and to an LDS copy of the
-//      panel (P, by column);
-//  (3) the trailing lower triangle A -= P P^T in FT x FT tiles, one wavefront per
-//      tile, on the matrix cores (16 x 16 x 4 products). Wavefront 0 takes the
-//      leading corner of the first tile, the next panel's diagonal block, and then
-//      factors that block (1) while the others finish the trailing update.
-// Matrix-core tiles are computed transposed (D[j][i] for the element (i, j)) so
-// that every lane group reads and writes 16 consecutive rows of a column of F.
-__global__ __launch_bounds__(FRONT_WG) void k_pgo_front(PgoDev d) {
-  __shared__ double P[FB * FRONT_MAX];  // panel: P[k * FRONT_MAX + i] = L(k0 + FB + i, k0 + k)
-  __shared__ int s_fail;
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int l16 = lane & 15, l4 = lane >> 4;
+__global__ __launch_bounds__(64) void k_front_inverse(PgoDev d, int kd) {
+  __shared__ double Ls[FB * (FB + 1)];
   if (*d.status != 0) return;
-  if (tid == 0) s_fail = 0;
-  __syncthreads();
-  const int n = d.nF;
+  front_inverse(d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd, d.Finv + (size_t)(kd / FB) * FB * FB, Ls);
+}
+
+__global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
+  if (*d.status != 0) return;
+  if (!front_factor(d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd) && threadIdx.x == 0) *d.status = 2;
+}
+
+// Rows i < nrow of P (by column: P[k * FT + i], row i of the panel's columns
+// k0..k0 + FB - 1) solved in place against the factored diagonal block:
+// L_kk x = a, right-looking, one thread per row (L_kk and 1 / L_jj from LDS).
+__device__ inline void front_solve_rows(double* P, int nrow, int t, const double* Ls, const double* rds) {
+  if (t >= nrow) return;
+  double x[FB];
+#pragma unroll
+  for (int c = 0; c < FB; ++c) x[c] = P[c * FT + t];
+#pragma unroll
+  for (int k = 0; k < FB; ++k) {
+    x[k] *= rds[k];
+#pragma unroll
+    for (int j = k + 1; j < FB; ++j) x[j] -= Ls[k * (FB + 1) + j] * x[k];
+  }
+#pragma unroll
+  for (int c = 0; c < FB; ++c) P[c * FT + t] = x[c];
+}
+
+// Panel k0 (its diagonal block factored by the previous launch) and the
+// trailing update it makes, one launch: workgroup b < ntile takes the FT x FT
+// tile (I, J) of the lower triangle from s0 = k0 + FB, solves the panel rows of
+// tile rows I and J against the diagonal block itself (rows are solved by every
+// tile that needs them, in parallel; tile (I, 0) stores row block I of the
+// panel), then A_IJ -= L_I L_J^T on the matrix cores, a 32 x 32 quadrant per
+// wavefront (16 x 16 x 4 products, computed transposed: the lane holds
+// D[jb + l4 + 4 v][ib + l16], so that each lane group reads and writes 16
+// consecutive rows of a column of F). The workgroup of tile (0, 0) then factors
+// the next diagonal block, which its first wavefront has just updated; the last
+// workgroup inverts the panel's diagonal block for the solves.
+__global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
+  __shared__ double Pa[FB * FT], Pb[FB * FT];  // panel rows of tile column J (a) and tile row I (b): [k][i]
+  __shared__ double Ls[FB * (FB + 1)];         // L_kk by column, strictly lower: Ls[c * (FB + 1) + i]
+  __shared__ double rds[FB];
+  if (*d.status != 0) return;
+  const int n = d.nF, s0 = k0 + FB, nr = n - s0;
+  const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
+  const int ti = (int)blockIdx.x, tid = (int)threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6, l16 = lane & 15, l4 = lane >> 4;
   double* F = d.F;
-  // pass k0 = -FB only factors the first diagonal block
-  for (int k0 = -FB; k0 < n; k0 += FB) {
-    if (s_fail) break;
-    const int s0 = k0 + FB, nr = n - s0;  // nr: a multiple of FB
-    // (2)
-    for (int ib = 16 * wv; k0 >= 0 && ib < nr; ib += 16 * (FRONT_WG / 64)) {
-      d4 x0 = {0.0, 0.0, 0.0, 0.0}, x1 = {0.0, 0.0, 0.0, 0.0};
-      double bv[FB / 4];
-#pragma unroll
-      for (int q = 0; q < FB / 4; ++q) bv[q] = F[(size_t)(k0 + 4 * q + l4) * n + s0 + ib + l16];
-#pragma unroll
-      for (int q = 0; q < FB / 4; ++q) {
-        // columns 0..15 of the inverse vanish beyond column 15
-        if (q < FB / 8) x0 = __builtin_amdgcn_mfma_f64_16x16x4f64(front_Vs[l16 * FB + 4 * q + l4], bv[q], x0, 0, 0, 0);
-        x1 = __builtin_amdgcn_mfma_f64_16x16x4f64(front_Vs[(16 + l16) * FB + 4 * q + l4], bv[q], x1, 0, 0, 0);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int c = l4 + 4 * v, i = ib + l16;
-        F[(size_t)(k0 + c) * n + s0 + i] = x0[v];
-        F[(size_t)(k0 + 16 + c) * n + s0 + i] = x1[v];
-        P[c * FRONT_MAX + i] = x0[v];
-        P[(16 + c) * FRONT_MAX + i] = x1[v];
-      }
-    }
-    __syncthreads();
-    // (3)
-    const int T = k0 >= 0 ? (nr + FT - 1) / FT : 0, ntile = T * (T + 1) / 2;
-    // part 0: all of the tile; 1: the blocks of its leading 32 x 32 corner; 2: the rest
-    auto tile = [&](int ti, int part) {
-      int I = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
-      I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
-      I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
-      const int J = ti - I * (I + 1) / 2;
-      // rows i in 64 I.., columns j in 64 J.. (relative to s0); 16 x 16 blocks (cj, ri),
-      // the lane holds D[jb + l4 + 4 v][ib + l16]
-      d4 acc[4][4];
-      bool live[4][4];
-#pragma unroll
-      for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-        for (int ri = 0; ri < 4; ++ri) {
-          const int ib = FT * I + 16 * ri, jb = FT * J + 16 * cj;
-          const bool corner = cj < 2 && ri < 2;
-          live[cj][ri] = ib < nr && jb < nr && (I != J || ri >= cj) && (part == 0 || (part == 1) == corner);
-          const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
-        }
-#pragma unroll 2
-      for (int k = 0; k < FB; k += 4) {
-        double pa[4], pb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          pa[q] = -P[(k + l4) * FRONT_MAX + FT * J + 16 * q + l16];
-          pb[q] = P[(k + l4) * FRONT_MAX + FT * I + 16 * q + l16];
-        }
-#pragma unroll
-        for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-          for (int ri = 0; ri < 4; ++ri)
-            if (live[cj][ri]) acc[cj][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[cj], pb[ri], acc[cj][ri], 0, 0, 0);
-      }
-#pragma unroll
-      for (int cj = 0; cj < 4; ++cj)
-#pragma unroll
-        for (int ri = 0; ri < 4; ++ri) {
-          if (!live[cj][ri]) continue;
-          const int ib = FT * I + 16 * ri, jb = FT * J + 16 * cj;
-          double* dst = F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16;
-#pragma unroll
-          for (int v = 0; v < 4; ++v)
-            if (I != J || ib + l16 >= jb + l4 + 4 * v) dst[(size_t)(4 * v) * n] = acc[cj][ri][v];
-        }
-    };
-    if (wv == 0) {
-      if (k0 < 0 || ntile > 0) {
-        if (k0 >= 0) {
-          tile(0, 1);
-          __threadfence_block();  // the corner's stores before the next diagonal block is read
-        }
-        if (!front_diag(F, n, s0, lane, d.Finv + (size_t)(s0 / FB) * FB * FB) &&
-            lane == 0)
-          s_fail = 1;
-      }
-    } else {
-      // item 0: the rest of tile 0; item t > 0: tile t
-      for (int it = wv - 1; it < ntile; it += FRONT_WG / 64 - 1) tile(it, it == 0 ? 2 : 0);
-    }
+  if (ti == ntile) {  // the panel's diagonal block inverse, for the solves
+    if (wv == 0) front_inverse(F, n, k0, lane, d.Frd + k0, d.Finv + (size_t)(k0 / FB) * FB * FB, Ls);
+    return;
+  }
+  int I = (int)((sqrtf(8.0f * (float)ti + 1.0f) - 1.0f) * 0.5f);
+  I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
+  I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
+  const int J = ti - I * (I + 1) / 2;
+  for (int x = tid; x < FB * FB; x += FRONT_TWG) {
+    const int c = x / FB, i = x % FB;
+    Ls[c * (FB + 1) + i] = i > c ? F[(size_t)(k0 + c) * n + k0 + i] : 0.0;
+  }
+  if (tid < FB) rds[tid] = d.Frd[k0 + tid];
+  for (int x = tid; x < FB * FT; x += FRONT_TWG) {
+    const int k = x / FT, i = x % FT;
+    const int ra = FT * J + i, rb = FT * I + i;  // rows relative to s0
+    Pa[x] = ra < nr ? F[(size_t)(k0 + k) * n + s0 + ra] : 0.0;
+    Pb[x] = rb < nr ? F[(size_t)(k0 + k) * n + s0 + rb] : 0.0;
+  }
+  __syncthreads();
+  const int na = min(FT, nr - FT * J), nb = min(FT, nr - FT * I);
+  if (tid < FT) front_solve_rows(Pa, na, tid, Ls, rds);
+  else if (tid < 2 * FT && I != J) front_solve_rows(Pb, nb, tid - FT, Ls, rds);
+  __syncthreads();
+  if (I == J) {  // one buffer serves both sides
+    for (int x = tid; x < FB * FT; x += FRONT_TWG) Pb[x] = Pa[x];
     __syncthreads();
   }
-  if (s_fail && tid == 0) *d.status = 2;
+  if (J == 0) {  // row block I of the panel, final
+    for (int x = tid; x < FB * FT; x += FRONT_TWG) {
+      const int k = x / FT, i = x % FT;
+      if (i < nb) F[(size_t)(k0 + k) * n + s0 + FT * I + i] = Pb[x];
+    }
+  }
+  const int qi = wv & 1, qj = wv >> 1;  // this wavefront's quadrant: row half qi, column half qj
+  d4 acc[2][2];
+  bool live[2][2];
+#pragma unroll
+  for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const int ib = FT * I + 32 * qi + 16 * ri, jb = FT * J + 32 * qj + 16 * cj;
+      live[cj][ri] = ib < nr && jb < nr && (I != J || ib >= jb);
+      const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
+    }
+#pragma unroll
+  for (int k = 0; k < FB; k += 4) {
+    double pa[2], pb[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      pa[q] = -Pa[(k + l4) * FT + 32 * qj + 16 * q + l16];
+      pb[q] = Pb[(k + l4) * FT + 32 * qi + 16 * q + l16];
+    }
+#pragma unroll
+    for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+      for (int ri = 0; ri < 2; ++ri)
+        if (live[cj][ri]) acc[cj][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[cj], pb[ri], acc[cj][ri], 0, 0, 0);
+  }
+#pragma unroll
+  for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      if (!live[cj][ri]) continue;
+      const int ib = FT * I + 32 * qi + 16 * ri, jb = FT * J + 32 * qj + 16 * cj;
+      double* dst = F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16;
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (ib != jb || ib + l16 >= jb + l4 + 4 * v) dst[(size_t)(4 * v) * n] = acc[cj][ri][v];
+    }
+  if (ti == 0 && wv == 0 && s0 < n) {  // the next diagonal block: quadrant (0, 0) of tile (0, 0), just stored
+    __threadfence_block();
+    if (!front_factor(F, n, s0, lane, d.Frd + s0) && lane == 0) *d.status = 2;
+  }
 }
 
 // Products of one solve level kept in LDS at a time.
@@ -1212,7 +1238,12 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
   }
   if (d.K > 0) {
     hipLaunchKernelGGL(k_pgo_clique_updates, dim3((d.n_dt + 3) / 4), dim3(256), 0, st, d);
-    hipLaunchKernelGGL(k_pgo_front, dim3(1), dim3(FRONT_WG), 0, st, d);
+    hipLaunchKernelGGL(k_front_diag, dim3(1), dim3(64), 0, st, d, 0);
+    for (int k0 = 0; k0 + FB < d.nF; k0 += FB) {
+      const int nr = d.nF - k0 - FB, T = (nr + FT - 1) / FT;
+      hipLaunchKernelGGL(k_front_update, dim3(T * (T + 1) / 2 + 1), dim3(FRONT_TWG), 0, st, d, k0);
+    }
+    hipLaunchKernelGGL(k_front_inverse, dim3(1), dim3(64), 0, st, d, d.nF - FB);
   }
   hipLaunchKernelGGL(k_pgo_finish, dim3(1), dim3(FIN_WG), 0, st, d, T, lambda, lm);
   return hipGetLastError();
@@ -1465,7 +1496,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
     total += bytes_of<s3a_sim3>(n_nodes);
     total += bytes_of<double>(56 * (size_t)E + 56);  // Aw
-    total += bytes_of<double>((size_t)S.nF * S.nF + 1) + bytes_of<double>((size_t)S.nF * FB + 1);  // front
+    total += bytes_of<double>((size_t)S.nF * S.nF + 1) + bytes_of<double>((size_t)S.nF * FB + 1) +
+             bytes_of<double>((size_t)S.nF + 1);  // front, its diagonal blocks' inverses, reciprocal pivots
     if (ws->buf) {
       (void)hipStreamSynchronize(st);
       (void)hipFree(ws->buf);
@@ -1542,6 +1574,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     ws->T_bak = carve<s3a_sim3>(c, n_nodes);
     d.F = carve<double>(c, (size_t)S.nF * S.nF + 1);
     d.Finv = carve<double>(c, (size_t)S.nF * FB + 1);
+    d.Frd = carve<double>(c, (size_t)S.nF + 1);
     for (auto& u : up) {
       e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return fail(last_hip, e);
