@@ -227,10 +227,13 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
             float x[7];
 #pragma unroll
             for (int j = 0; j < 7; ++j) x[j] = HV::elem(raw, j, e);
-            const bool valid =
-                P.active && rel0 + e >= lo_rel && rel0 + e < end_rel && finite7(x) && x[6] >= tau;
+            // elements outside the pair (a run's first and last vectors) are zeroed on a
+            // branch the other vectors skip: they add nothing, whatever they hold
+            const bool in = P.active && rel0 + e >= lo_rel && rel0 + e < end_rel;
+            if (!in) {
 #pragma unroll
-            for (int j = 0; j < 7; ++j) x[j] = valid ? x[j] : 0.0f;  // masked points add zeros
+              for (int j = 0; j < 7; ++j) x[j] = 0.0f;
+            }
             double y[3], r[3];
 #pragma unroll
             for (int i = 0; i < 3; ++i) {
@@ -238,8 +241,18 @@ __global__ __launch_bounds__(WG) void k_hess(Shape sh, const CallDesc* __restric
                          fma(P.M[3 * i + 1], (double)x[1], fma(P.M[3 * i + 2], (double)x[2], P.t[i])));
               r[i] = y[i] - (double)x[3 + i];
             }
-            const double c = x[6];
-            const double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            double e2 = r[0] * r[0] + r[1] * r[1] + r[2] * r[2];
+            // a NaN/Inf in p or q makes e2 NaN/Inf (FP64 sums of FP32 values cannot
+            // overflow), so two checks find every non-finite point; such a point is
+            // zeroed on a branch that wavefronts without one skip
+            bool valid = in && x[6] >= tau;
+            if (!(__builtin_isfinite(e2) && __builtin_isfinite(x[6]))) {
+              valid = false;
+#pragma unroll
+              for (int i = 0; i < 3; ++i) y[i] = r[i] = 0.0;
+              e2 = 0.0;
+            }
+            const double c = valid ? (double)x[6] : 0.0;  // invalid points weigh nothing
             // 1 / |r|, used only outside delta (|r| > delta > 0): the hardware
             // estimate and one Newton step (relative error near 1e-14)
             double ie = __builtin_amdgcn_rsq(e2);
