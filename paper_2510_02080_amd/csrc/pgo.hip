@@ -595,6 +595,12 @@ __device__ __attribute__((always_inline)) inline bool front_factor(double* F, in
   for (int k = 0; k < FB; ++k) {
     double* cur = cb + (k & 1) * (FB + 1);
     double* nxt = cb + ((k + 1) & 1) * (FB + 1);
+    // the column's entries below the pivot, all read before the pivot's chain
+    // (their LDS latency overlaps it instead of each read waiting in turn)
+    double cv[FB];
+#pragma unroll
+    for (int j = k + 1; j < FB; ++j) cv[j] = cur[j];
+    __builtin_amdgcn_sched_barrier(0);
     const double dkk = readlane_f64(a[k], k);
     ok = ok && dkk > 0.0;
     const double x = dkk > 0.0 ? dkk : 1.0;
@@ -606,11 +612,11 @@ __device__ __attribute__((always_inline)) inline bool front_factor(double* F, in
     rv = lane == k ? rk : rv;
     const double m = a[k] * rk;  // L_rk / L_kk, and L_jk = cur[j] / L_kk
     if (k + 1 < FB) {
-      a[k + 1] -= m * cur[k + 1];
+      a[k + 1] -= m * cv[k + 1];
       nxt[e] = a[k + 1];
     }
 #pragma unroll
-    for (int j = k + 2; j < FB; ++j) a[j] -= m * cur[j];
+    for (int j = k + 2; j < FB; ++j) a[j] -= m * cv[j];
     wave_sync();
   }
   if (lane < FB) {
@@ -668,9 +674,13 @@ __device__ inline void front_solve_rows(double* P, int nrow, int t, const double
   for (int c = 0; c < FB; ++c) x[c] = P[c * FT + t];
 #pragma unroll
   for (int k = 0; k < FB; ++k) {
+    double lk[FB];  // column k of L_kk below the diagonal, read as one batch
+#pragma unroll
+    for (int j = k + 1; j < FB; ++j) lk[j] = Ls[k * (FB + 1) + j];
+    __builtin_amdgcn_sched_barrier(0);
     x[k] *= rds[k];
 #pragma unroll
-    for (int j = k + 1; j < FB; ++j) x[j] -= Ls[k * (FB + 1) + j] * x[k];
+    for (int j = k + 1; j < FB; ++j) x[j] -= lk[j] * x[k];
   }
 #pragma unroll
   for (int c = 0; c < FB; ++c) P[c * FT + t] = x[c];
