@@ -88,8 +88,8 @@ __device__ inline void block_store_h(double (&acc)[HSTAT], double (*red)[HSTAT],
 }
 
 // The Hessian pass reads 8-byte vectors per plane (2 FP32 or 4 BF16 points):
-// its FP64 sums need 104 registers per lane, and half-width raw buffers and
-// fewer points in flight per lane let more wavefronts share a SIMD.
+// its per-lane sums take 74 registers, and half-width raw buffers and fewer
+// points in flight per lane let three wavefronts share a SIMD.
 typedef unsigned int s3a_u2 __attribute__((ext_vector_type(2)));
 template <int DT>
 struct HalfVec;

@@ -15,9 +15,10 @@
 // factor blocks update which target block.
 // Device, per iteration: the edges are linearised and H and g assembled across
 // the chip; the sparse columns are factored level by level, two launches per
-// level spread over the chip (the columns of a level are independent); the
-// dense trailing clique is factored by one workgroup on the matrix cores; one
-// workgroup solves L L^T dx = -g and applies T <- Exp(dx) T.
+// level spread over the chip (the columns of a level are independent), each
+// column's forward solve with its factor; the dense trailing clique is factored
+// one panel per launch, its tiles across the chip on the matrix cores; one
+// workgroup finishes the solves of L L^T dx = -g and applies T <- Exp(dx) T.
 #include <string.h>
 
 #include <algorithm>
@@ -1228,9 +1229,10 @@ int fail(int* last_hip, hipError_t e) {
 namespace {
 
 // One damped solve and update of the poses (or, without update, only chi^2 at the
-// current linearisation): assembly across the chip, the sparse factorisation in one
-// workgroup, the clique's sparse-column updates across the chip, then the clique, the
-// solves and the update in one workgroup.
+// current linearisation): assembly across the chip, the sparse factorisation and
+// forward solve level by level across the chip, the clique's sparse-column updates
+// across the chip, the clique one panel per launch, then the rest of the solves and
+// the update in one workgroup.
 hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, const std::vector<int32_t>& ct,
                             s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
   hipLaunchKernelGGL(k_pgo_chi2, dim3(1), dim3(PGO_WG), 0, st, d, it);
