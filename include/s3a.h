@@ -329,8 +329,8 @@ typedef struct {
 /*
  * Sim(3) pose-graph optimisation (Sec. III-E) with Huber edge weights and a
  * 7x7-block sparse Cholesky factorisation in FP64 on the GPU (minimum-degree
- * order; a dense trailing clique of up to 72 nodes is factored as one dense
- * block on the matrix cores).
+ * order; a dense trailing clique, with the columns before it that fit in its
+ * padding, up to 73 nodes, is factored as one dense block on the matrix cores).
  * Gauss-Newton (default): exactly iters steps of (H + lambda diag(H)) dx = -g.
  * S3A_PGO_LM, Levenberg-Marquardt: each trial solves the same system with the
  * current lambda; it is kept when the energy F = sum rho(sqrt(e^T Omega e))

@@ -67,13 +67,17 @@ struct PgoDev {
   const int32_t* fu_ptr; const int32_t* fu_a; const int32_t* fu_b;
   const int32_t* fs_ptr; const int32_t* fs_blk;
   const int32_t* bs_ptr; const int32_t* bs_blk;
-  // dense trailing clique: columns p0 .. m-1 (K of them) hold every block below the
-  // diagonal. Its blocks, with the updates of the sparse columns applied (dt lists),
+  // dense front: the trailing columns p0 .. m-1 (K of them: a clique, each column
+  // holding every block below the diagonal, and the columns before it that fit in its
+  // padding). Its blocks, with the updates of the sparse columns applied (dt lists),
   // form the dense front F (order nF = 7 K padded with identity to a multiple of the
-  // update tile, column-major, lower triangle), factored in place; Finv holds the
-  // inverses of the front's FB x FB diagonal blocks (row-major) for the solves.
-  int32_t K, p0, n_dt, nF;
+  // update tile, column-major, lower triangle), factored in place; the lower blocks
+  // outside the structure (fz_rc: front-relative node row and column) and the padding
+  // are rewritten every iteration. Finv holds the inverses of the front's FB x FB
+  // diagonal blocks (row-major) for the solves.
+  int32_t K, p0, n_dt, nF, n_fz;
   const int32_t* dt_tgt; const int32_t* dt_ptr; const int32_t* dup_a; const int32_t* dup_b;
+  const int32_t* fz_rc;
   double* F;
   double* Finv;
   double* Frd;    // [nF] 1 / L_jj of the front's factor
@@ -286,7 +290,7 @@ __device__ inline double wg_sum(double v, double* sh) {
 
 // Dense front of the trailing clique: at most PGO_KMAX node columns; panels of FB
 // columns, trailing updates in FT x FT tiles.
-constexpr int PGO_KMAX = 72;
+constexpr int PGO_KMAX = 73;
 constexpr int FB = 32;
 constexpr int FT = 64;
 constexpr int FRONT_MAX = 512;
@@ -531,17 +535,77 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
   }
 }
 
-// The clique's blocks with the sparse columns' updates applied, written into the
-// dense front: independent targets, one wavefront each, spread over the whole chip.
+// Everything the front needs from the sparse part, one wavefront per item, spread
+// over the whole chip (the items are independent):
+//   [0, n_dt)              a front block with the sparse columns' updates applied;
+//   [n_dt, + n_fz)         a lower block outside the structure, zero;
+//   [.., + K)              front node row i's right-hand side after the sparse
+//                          columns' forward solve, y_i - sum over sparse k of L_ik y_k
+//                          (in place in g: these waves read only the sparse part);
+//   [.., + pad waves)      the padding rows' lower entries, identity.
 __global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
   if (*d.status != 0) return;
-  const int ti = (blockIdx.x * blockDim.x + threadIdx.x) >> 6, lane = threadIdx.x & 63;
-  if (ti >= d.n_dt) return;
-  const int t = d.dt_tgt[ti];
-  const int row = t < d.m ? t : d.blk_row[t - d.m], col = t < d.m ? t : d.blk_col[t - d.m];
+  int ti = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
   const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
-  double* dst = d.F + (size_t)(7 * (col - d.p0) + s) * d.nF + 7 * (row - d.p0) + r;
-  update_target(d, target_elem(d, t, lane), dst, d.dt_ptr[ti], d.dt_ptr[ti + 1], d.dup_a, d.dup_b, lane);
+  if (ti < d.n_dt) {
+    const int t = d.dt_tgt[ti];
+    const int row = t < d.m ? t : d.blk_row[t - d.m], col = t < d.m ? t : d.blk_col[t - d.m];
+    double* dst = d.F + (size_t)(7 * (col - d.p0) + s) * d.nF + 7 * (row - d.p0) + r;
+    update_target(d, target_elem(d, t, lane), dst, d.dt_ptr[ti], d.dt_ptr[ti + 1], d.dup_a, d.dup_b, lane);
+    return;
+  }
+  ti -= d.n_dt;
+  if (ti < d.n_fz) {
+    const int row = d.fz_rc[2 * ti], col = d.fz_rc[2 * ti + 1];
+    if (lane < 49) d.F[(size_t)(7 * col + s) * d.nF + 7 * row + r] = 0.0;
+    return;
+  }
+  ti -= d.n_fz;
+  if (ti < d.K) {
+    const int c = d.p0 + ti;
+    double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int q = d.row_ptr[c] + lane; q < d.row_ptr[c + 1]; q += 64) {
+      const int b = d.row_blk[q];
+      const int k = d.blk_col[b];
+      if (k >= d.p0) continue;
+      const double* L = d.Lb + 49 * b;
+      const double* y = d.g + 7 * k;
+      double yv[7];
+#pragma unroll
+      for (int u = 0; u < 7; ++u) yv[u] = y[u];
+#pragma unroll
+      for (int i = 0; i < 7; ++i)
+#pragma unroll
+        for (int u = 0; u < 7; ++u) acc[i] += L[7 * i + u] * yv[u];
+    }
+    wave_totals_f64(acc);
+    if (lane < 7) {
+      double a = acc[0];
+#pragma unroll
+      for (int i = 1; i < 7; ++i) a = lane == i ? acc[i] : a;
+      d.g[7 * c + lane] -= a;
+    }
+    return;
+  }
+  ti -= d.K;
+  // padding rows nK .. nF-1, columns 0 .. row: 256 entries per wavefront, row by row
+  const int n = d.nF, nK = 7 * d.K;
+  const int64_t n_pad = (int64_t)(n - nK) * (n + nK + 1) / 2;
+  for (int64_t x = (int64_t)ti * 256 + lane; x < min((int64_t)(ti + 1) * 256, n_pad); x += 64) {
+    // row nK + j starts at offset j (2 nK + j + 1) / 2
+    int j = (int)((sqrt(8.0 * (double)x + (2.0 * nK + 1) * (2.0 * nK + 1)) - (2.0 * nK + 1)) * 0.5);
+    while (j > 0 && (int64_t)j * (2 * nK + j + 1) / 2 > x) --j;
+    while ((int64_t)(j + 1) * (2 * nK + j + 2) / 2 <= x) ++j;
+    const int row = nK + j, col = (int)(x - (int64_t)j * (2 * nK + j + 1) / 2);
+    d.F[(size_t)col * n + row] = row == col ? 1.0 : 0.0;
+  }
+}
+
+// Wavefronts of k_pgo_clique_updates.
+inline int64_t clique_update_waves(const PgoDev& d) {
+  const int64_t n_pad = (int64_t)(d.nF - 7 * d.K) * (d.nF + 7 * d.K + 1) / 2;
+  return (int64_t)d.n_dt + d.n_fz + d.K + (n_pad + 255) / 256;
 }
 
 // Identity padding of the front (rows and columns 7 K .. nF-1), zeros elsewhere.
@@ -864,29 +928,11 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
   __shared__ double prod[7 * SOLVE_CHUNK];
   const int tid = threadIdx.x;
   if (*d.status != 0) return;
-  const int lane = tid & 63, wv = tid >> 6;
   // (the forward solve over the sparse columns ran with their factorisation, k_pgo_level_factor)
   if (d.K > 0) {
     const int n = d.nF, nK = 7 * d.K;
-    // ---- the clique rows: y_i - sum over sparse columns k of L_ik y_k, into LDS
-    for (int i = wv; i < d.K; i += FIN_WG / 64) {
-      const int c = d.p0 + i;
-      double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-      for (int q = d.row_ptr[c] + lane; q < d.row_ptr[c + 1]; q += 64) {
-        const int b = d.row_blk[q];
-        const int k = d.blk_col[b];
-        if (k >= d.p0) continue;
-        const double* L = d.Lb + 49 * b;
-        const double* y = d.g + 7 * k;
-        for (int r = 0; r < 7; ++r)
-          for (int u = 0; u < 7; ++u) acc[r] += L[7 * r + u] * y[u];
-      }
-      wave_totals_f64(acc);
-      if (lane == 0)
-#pragma unroll
-        for (int r = 0; r < 7; ++r) ys[7 * i + r] = d.g[7 * c + r] - acc[r];
-    }
-    for (int x = nK + tid; x < n; x += FIN_WG) ys[x] = 0.0;
+    // ---- the front rows' right-hand side (k_pgo_clique_updates left it in g), into LDS
+    for (int x = tid; x < n; x += FIN_WG) ys[x] = x < nK ? d.g[7 * d.p0 + x] : 0.0;
     __syncthreads();
     // ---- forward through the front: y_blk = L_blk^{-1} y_blk, then the rows below
     for (int k0 = 0; k0 < n; k0 += FB) {
@@ -972,7 +1018,8 @@ struct Symbolic {
   int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
       up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_tgt, row_ptr, row_blk,
-      chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b, ct_ptr;
+      chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b, ct_ptr,
+      fz_rc;
   std::vector<int8_t> gv_sign;
 };
 
@@ -1107,10 +1154,27 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   for (int c = m - 1; c >= 0 && (int)cs[c].size() == m - 1 - c; --c) ++K;
   if (K < 8) K = 0;
   if (K > PGO_KMAX) K = PGO_KMAX;  // the last PGO_KMAX columns of a larger clique are one too
+  // The columns just before the clique join the front while they fit in its identity
+  // padding: the dense factor costs the same, and each one taken off the sparse
+  // schedule can shorten it by a level. Their rows all lie below them, so in the
+  // front; the blocks their structure lacks are exact zeros of L too (the symbolic
+  // factor is closed under elimination) and are rewritten as zeros every iteration.
+  if (K > 0) {
+    const int nF0 = (7 * K + FT - 1) / FT * FT;
+    while (K < m && K < PGO_KMAX && 7 * (K + 1) <= nF0) ++K;
+  }
   const int p0 = m - K;
   S.K = K;
   S.p0 = p0;
   S.nF = K > 0 ? (7 * K + FT - 1) / FT * FT : 0;
+  for (int c = p0; c < m; ++c) {  // the front's lower blocks outside the structure
+    int r = c + 1;
+    for (int x : cs[c]) {
+      for (; r < x; ++r) S.fz_rc.insert(S.fz_rc.end(), {r - p0, c - p0});
+      r = x + 1;
+    }
+    for (; r < m; ++r) S.fz_rc.insert(S.fz_rc.end(), {r - p0, c - p0});
+  }
   // schedule of the sparse columns (levels without one are dropped)
   S.flev_ptr.assign(1, 0);
   S.ct_ptr.assign(1, 0);
@@ -1249,7 +1313,7 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
     hipLaunchKernelGGL(k_pgo_level_factor, dim3(std::min(ncol, 1024)), dim3(LEV_WG), 0, st, d, l);
   }
   if (d.K > 0) {
-    hipLaunchKernelGGL(k_pgo_clique_updates, dim3((d.n_dt + 3) / 4), dim3(256), 0, st, d);
+    hipLaunchKernelGGL(k_pgo_clique_updates, dim3((unsigned)((clique_update_waves(d) + 3) / 4)), dim3(256), 0, st, d);
     hipLaunchKernelGGL(k_front_diag, dim3(1), dim3(64), 0, st, d, 0);
     for (int k0 = 0; k0 + FB < d.nF; k0 += FB) {
       const int nr = d.nF - k0 - FB, T = (nr + FT - 1) / FT;
@@ -1494,7 +1558,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.up_ptr.size()) + bytes_of<int32_t>(S.up_a.size()) * 2;
     total += bytes_of<int32_t>(S.flev_ptr.size()) + bytes_of<int32_t>(S.flev_col.size() + 1);
     total += bytes_of<int32_t>(S.dt_tgt.size() + 1) + bytes_of<int32_t>(S.dt_ptr.size());
-    total += bytes_of<int32_t>(S.dup_a.size() + 1) * 2;
+    total += bytes_of<int32_t>(S.dup_a.size() + 1) * 2 + bytes_of<int32_t>(S.fz_rc.size() + 2);
     total += bytes_of<int32_t>(S.lt_tgt.size() + 1) + bytes_of<int32_t>(S.ct_ptr.size());
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
@@ -1552,6 +1616,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_dtp = carve<int32_t>(c, S.dt_ptr.size()); put(p_dtp, S.dt_ptr); d.dt_ptr = p_dtp;
     int32_t* p_dua = carve<int32_t>(c, S.dup_a.size() + 1); put(p_dua, S.dup_a); d.dup_a = p_dua;
     int32_t* p_dub = carve<int32_t>(c, S.dup_b.size() + 1); put(p_dub, S.dup_b); d.dup_b = p_dub;
+    int32_t* p_fz = carve<int32_t>(c, S.fz_rc.size() + 2); put(p_fz, S.fz_rc); d.fz_rc = p_fz;
+    d.n_fz = (int32_t)(S.fz_rc.size() / 2);
     int32_t* p_ltt = carve<int32_t>(c, S.lt_tgt.size() + 1); put(p_ltt, S.lt_tgt); d.lt_tgt = p_ltt;
     int32_t* p_ctp = carve<int32_t>(c, S.ct_ptr.size()); put(p_ctp, S.ct_ptr); d.ct_ptr = p_ctp;
     int32_t* p_rwp = carve<int32_t>(c, S.row_ptr.size()); put(p_rwp, S.row_ptr); d.row_ptr = p_rwp;

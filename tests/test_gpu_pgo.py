@@ -192,7 +192,7 @@ def test_complete_graphs(h, n):
     """Complete graphs: every free node belongs to one dense clique, which is
     factored as a dense front. With 9 and 20 free nodes the front is the whole
     system and there are no sparse columns. With 79 free nodes the front takes
-    the last 72, and the other 7 are sparse columns, whose update lists fill
+    the last 73, and the other 6 are sparse columns, whose update lists fill
     more than one chunk of products."""
     rng = np.random.default_rng(100 + n)
     Tgt = np.array([np.eye(4)] + [rand_pose(rng) for _ in range(n - 1)])
