@@ -67,6 +67,16 @@ struct PgoDev {
   const int32_t* fu_ptr; const int32_t* fu_a; const int32_t* fu_b;
   const int32_t* fs_ptr; const int32_t* fs_blk;
   const int32_t* bs_ptr; const int32_t* bs_blk;
+  const int32_t* bs_row;  // row node of each bs_blk entry
+  // per level, LVW entries: j0, j1 (schedule positions), Q0 = bs_ptr[j0], Q1 = bs_ptr[j1],
+  // then, when bw is kept, the offsets in bw of the level's blocks and columns and their
+  // strides NQ, NJ (the counts rounded up to a wavefront)
+  const int32_t* lv;
+  // the backward solve's copy of the factor, level by level, element-major: element e of
+  // the level's block p at [lv[4] + e NQ + p]; of its column p, the lower triangle of
+  // L_cc^{-1} by rows (e < 28) and y (28 + r) at [lv[5] + e NJ + p]. Null when not kept.
+  double* bw;
+  int64_t bw_size;
   // dense front: the trailing columns p0 .. m-1 (K of them: a clique, each column
   // holding every block below the diagonal, and the columns before it that fit in its
   // padding). Its blocks, with the updates of the sparse columns applied (dt lists),
@@ -81,6 +91,8 @@ struct PgoDev {
   double* F;
   double* Finv;
   double* Frd;    // [nF] 1 / L_jj of the front's factor
+  double* yF;     // [nF] the front's right-hand side, updated panel by panel by the forward solve
+  double* zF;     // [nF] the front's forward solve L_F z = y, block by block
   // rows of L: blocks (c, k), k < c (the clique rows' right-hand side)
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
@@ -348,10 +360,11 @@ __device__ inline void update_target(const PgoDev& d, const double* src, double*
 }
 
 // In-place Cholesky of one 7x7 diagonal block by one lane (row by row), zeroing
-// the upper triangle, and the inverse of the factor into Di (and `copy` when
-// given): each diagonal element is inverted once, so the triangular solves that
-// use the block need no divisions. False if a pivot is not positive.
-__device__ inline bool chol7_lane(double* D, double* Di, double* copy) {
+// the upper triangle, and the inverse of the factor into Di (and its lower
+// triangle, row by row, to copy[e * cstride] when given): each diagonal element is
+// inverted once, so the triangular solves that use the block need no divisions.
+// False if a pivot is not positive.
+__device__ inline bool chol7_lane(double* D, double* Di, double* copy, int cstride) {
   double L[7][7];
   double rinv[7];
   bool ok = true;
@@ -392,15 +405,15 @@ __device__ inline bool chol7_lane(double* D, double* Di, double* copy) {
         v[i] = -t * rinv[i];
       }
       Di[7 * i + j] = v[i];
-      if (copy) copy[7 * i + j] = v[i];
+      if (copy && i >= j) copy[(i * (i + 1) / 2 + j) * cstride] = v[i];
     }
   }
   return ok;
 }
 
 // One row of L_ij = S_ij L_jj^{-T} in place, with Dinv = L_jj^{-1}; optionally
-// copied to `copy` as well.
-__device__ inline void trsm_row(double* row, const double* Dinv, double* copy) {
+// copied to copy[j * cstride] as well.
+__device__ inline void trsm_row(double* row, const double* Dinv, double* copy, int cstride) {
   double x[7], y[7];
 #pragma unroll
   for (int k = 0; k < 7; ++k) x[k] = row[k];
@@ -415,7 +428,7 @@ __device__ inline void trsm_row(double* row, const double* Dinv, double* copy) {
   for (int j = 0; j < 7; ++j) row[j] = y[j];
   if (copy)
 #pragma unroll
-    for (int j = 0; j < 7; ++j) copy[j] = y[j];
+    for (int j = 0; j < 7; ++j) copy[j * cstride] = y[j];
 }
 
 // Assembly of the normal equations from the per-edge linearisations:
@@ -466,6 +479,11 @@ __global__ __launch_bounds__(PGO_WG) void k_pgo_chi2(PgoDev d, int it) {
 //    diagonal block, and one thread per row forms the off-diagonal rows
 //    L_ij = S_ij L_jj^{-T}.
 constexpr int LEV_WG = 256;
+constexpr int LVW = 8;  // entries per level of the level table
+// A level's entries of the table, passed to its factor launch by value.
+struct LevelArg {
+  int j0, Q0, lb, dc, NQ, NJ;
+};
 __global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
   if (*d.status != 0) return;
   const int lane = threadIdx.x & 63;
@@ -477,14 +495,18 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
   }
 }
 
-__global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
+__global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, LevelArg la) {
   if (*d.status != 0) return;
   __shared__ int s_fail;
   __shared__ double part[LEV_WG / 64][7];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = d.flev_ptr[l] + (int)blockIdx.x; j < d.flev_ptr[l + 1]; j += (int)gridDim.x) {
     const int col = d.flev_col[j];
-    if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, nullptr) ? 0 : 1;
+    // the backward solve's copy of this column (level-major, element-major: one
+    // coalesced read per element for a level's columns and blocks)
+    const int pj = j - la.j0, NJ = la.NJ;
+    double* bwc = d.bw ? d.bw + la.dc + pj : nullptr;
+    if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, bwc, NJ) ? 0 : 1;
     // forward solve of this column, y_c = L_cc^{-1} (y_c - sum_k L_ck y_k): its row blocks
     // (c, k) lie in factored columns of lower levels, whose y_k are final; per-thread
     // sums over the blocks (strided), then a fixed tree
@@ -526,11 +548,14 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
 #pragma unroll
         for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
         d.g[7 * col + r] = t;
+        if (bwc) bwc[(28 + r) * NJ] = t;
       }
     }
     const int b0 = d.col_ptr[col], nb = d.col_ptr[col + 1] - b0;
+    const int pq = d.bs_ptr[j] - la.Q0, NQ = la.NQ;
     for (int x = (int)threadIdx.x; x < 7 * nb; x += LEV_WG)
-      trsm_row(d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7), d.Di + 49 * col, nullptr);
+      trsm_row(d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7), d.Di + 49 * col,
+               d.bw ? d.bw + la.lb + 7 * (x % 7) * NQ + pq + x / 7 : nullptr, NQ);
     __syncthreads();
   }
 }
@@ -540,9 +565,10 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l) {
 //   [0, n_dt)              a front block with the sparse columns' updates applied;
 //   [n_dt, + n_fz)         a lower block outside the structure, zero;
 //   [.., + K)              front node row i's right-hand side after the sparse
-//                          columns' forward solve, y_i - sum over sparse k of L_ik y_k
-//                          (in place in g: these waves read only the sparse part);
-//   [.., + pad waves)      the padding rows' lower entries, identity.
+//                          columns' forward solve, y_i - sum over sparse k of L_ik y_k,
+//                          into yF;
+//   [.., + pad waves)      the padding rows' lower entries, identity (and their
+//                          right-hand side, zero).
 __global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
   if (*d.status != 0) return;
   int ti = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
@@ -584,13 +610,15 @@ __global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
       double a = acc[0];
 #pragma unroll
       for (int i = 1; i < 7; ++i) a = lane == i ? acc[i] : a;
-      d.g[7 * c + lane] -= a;
+      d.yF[7 * ti + lane] = d.g[7 * c + lane] - a;
     }
     return;
   }
   ti -= d.K;
-  // padding rows nK .. nF-1, columns 0 .. row: 256 entries per wavefront, row by row
+  // padding rows nK .. nF-1 (fewer than FT): zero right-hand side; their lower
+  // entries, columns 0 .. row: 256 per wavefront, row by row
   const int n = d.nF, nK = 7 * d.K;
+  if (ti == 0 && nK + lane < n) d.yF[nK + lane] = 0.0;
   const int64_t n_pad = (int64_t)(n - nK) * (n + nK + 1) / 2;
   for (int64_t x = (int64_t)ti * 256 + lane; x < min((int64_t)(ti + 1) * 256, n_pad); x += 64) {
     // row nK + j starts at offset j (2 nK + j + 1) / 2
@@ -718,10 +746,31 @@ __device__ __noinline__ void front_inverse(const double* F, int n, int kd, int l
   }
 }
 
+// Forward substitution z = L_kk^{-1} y through a factored FB x FB diagonal block
+// (strictly lower part by column in Ls, 1 / L_jj in rd), by one wavefront: lane
+// i < FB holds y_i on entry and z_i on return.
+__device__ inline double front_subst(double v, const double* Ls, const double* rd, int lane) {
+#pragma unroll
+  for (int k = 0; k < FB; ++k) {
+    const double zk = readlane_f64(v, k) * rd[k];
+    if (lane > k && lane < FB) v -= Ls[k * (FB + 1) + lane] * zk;
+    v = lane == k ? zk : v;
+  }
+  return v;
+}
+
+// The last diagonal block: its inverse (for the backward solve) and the last
+// block of the forward solve, z = L_kk^{-1} y.
 __global__ __launch_bounds__(64) void k_front_inverse(PgoDev d, int kd) {
   __shared__ double Ls[FB * (FB + 1)];
+  __shared__ double rds[FB];
   if (*d.status != 0) return;
-  front_inverse(d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd, d.Finv + (size_t)(kd / FB) * FB * FB, Ls);
+  const int lane = (int)threadIdx.x;
+  front_inverse(d.F, d.nF, kd, lane, d.Frd + kd, d.Finv + (size_t)(kd / FB) * FB * FB, Ls);
+  if (lane < FB) rds[lane] = d.Frd[kd + lane];
+  wave_sync();
+  const double v = front_subst(lane < FB ? d.yF[kd + lane] : 0.0, Ls, rds, lane);
+  if (lane < FB) d.zF[kd + lane] = v;
 }
 
 __global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
@@ -732,20 +781,29 @@ __global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
 // Rows i < nrow of P (by column: P[k * FT + i], row i of the panel's columns
 // k0..k0 + FB - 1) solved in place against the factored diagonal block:
 // L_kk x = a, right-looking, one thread per row (L_kk and 1 / L_jj from LDS).
-__device__ inline void front_solve_rows(double* P, int nrow, int t, const double* Ls, const double* rds) {
+__device__ __attribute__((always_inline)) inline void front_solve_rows(double* P, int nrow, int t, const double* Ls,
+                                                                    const double* rds) {
   if (t >= nrow) return;
-  double x[FB];
+  double x[FB], rd[FB];
 #pragma unroll
   for (int c = 0; c < FB; ++c) x[c] = P[c * FT + t];
 #pragma unroll
-  for (int k = 0; k < FB; ++k) {
-    double lk[FB];  // column k of L_kk below the diagonal, read as one batch
+  for (int c = 0; c < FB; ++c) rd[c] = rds[c];
+  // column k of L_kk below the diagonal, read one step ahead of its use
+  double lk[FB];
 #pragma unroll
-    for (int j = k + 1; j < FB; ++j) lk[j] = Ls[k * (FB + 1) + j];
+  for (int j = 1; j < FB; ++j) lk[j] = Ls[j];
+#pragma unroll
+  for (int k = 0; k < FB; ++k) {
+    double ln[FB];
+#pragma unroll
+    for (int j = k + 2; j < FB; ++j) ln[j] = Ls[(k + 1) * (FB + 1) + j];
     __builtin_amdgcn_sched_barrier(0);
-    x[k] *= rds[k];
+    x[k] *= rd[k];
 #pragma unroll
     for (int j = k + 1; j < FB; ++j) x[j] -= lk[j] * x[k];
+#pragma unroll
+    for (int j = k + 2; j < FB; ++j) lk[j] = ln[j];
   }
 #pragma unroll
   for (int c = 0; c < FB; ++c) P[c * FT + t] = x[c];
@@ -766,6 +824,7 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
   __shared__ double Pa[FB * FT], Pb[FB * FT];  // panel rows of tile column J (a) and tile row I (b): [k][i]
   __shared__ double Ls[FB * (FB + 1)];         // L_kk by column, strictly lower: Ls[c * (FB + 1) + i]
   __shared__ double rds[FB];
+  __shared__ double zs[FB];  // the panel's block of the forward solve
   if (*d.status != 0) return;
   const int n = d.nF, s0 = k0 + FB, nr = n - s0;
   const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
@@ -780,19 +839,45 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
   I -= (I * (I + 1) / 2 > ti) ? 1 : 0;
   I += ((I + 1) * (I + 2) / 2 <= ti) ? 1 : 0;
   const int J = ti - I * (I + 1) / 2;
-  for (int x = tid; x < FB * FB; x += FRONT_TWG) {
-    const int c = x / FB, i = x % FB;
-    Ls[c * (FB + 1) + i] = i > c ? F[(size_t)(k0 + c) * n + k0 + i] : 0.0;
+  const bool fwd = J == 0 && wv == 1;  // this wavefront carries the forward solve through the panel
+  const int nb = min(FT, nr - FT * I);
+  double yk = 0.0, yi = 0.0;
+  if (fwd) {  // y of the panel's block and of tile row I, read early (their latency overlaps the loads below)
+    if (lane < FB) yk = d.yF[k0 + lane];
+    if (lane < nb) yi = d.yF[s0 + FT * I + lane];
   }
-  if (tid < FB) rds[tid] = d.Frd[k0 + tid];
-  for (int x = tid; x < FB * FT; x += FRONT_TWG) {
-    const int k = x / FT, i = x % FT;
-    const int ra = FT * J + i, rb = FT * I + i;  // rows relative to s0
-    Pa[x] = ra < nr ? F[(size_t)(k0 + k) * n + s0 + ra] : 0.0;
-    Pb[x] = rb < nr ? F[(size_t)(k0 + k) * n + s0 + rb] : 0.0;
+  {  // every load issued before any is used (rows past the front's end read the next
+     // column's top, in bounds since the panel is not the last, and are zeroed)
+    constexpr int NL = FB * FB / FRONT_TWG, NP = FB * FT / FRONT_TWG;
+    double vl[NL], va[NP], vb[NP];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int x = tid + u * FRONT_TWG, c = x / FB, i = x % FB;
+      vl[u] = F[(size_t)(k0 + c) * n + k0 + i];
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int x = tid + u * FRONT_TWG, k = x / FT, i = x % FT;
+      va[u] = F[(size_t)(k0 + k) * n + s0 + FT * J + i];
+      vb[u] = F[(size_t)(k0 + k) * n + s0 + FT * I + i];
+    }
+    const double rv = tid < FB ? d.Frd[k0 + tid] : 0.0;
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+      const int x = tid + u * FRONT_TWG, c = x / FB, i = x % FB;
+      Ls[c * (FB + 1) + i] = i > c ? vl[u] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < NP; ++u) {
+      const int x = tid + u * FRONT_TWG, i = x % FT;
+      Pa[x] = FT * J + i < nr ? va[u] : 0.0;
+      Pb[x] = FT * I + i < nr ? vb[u] : 0.0;
+    }
+    if (tid < FB) rds[tid] = rv;
   }
+  static_assert(FB * FB % FRONT_TWG == 0 && FB * FT % FRONT_TWG == 0, "whole rounds of loads");
   __syncthreads();
-  const int na = min(FT, nr - FT * J), nb = min(FT, nr - FT * I);
+  const int na = min(FT, nr - FT * J);
   if (tid < FT) front_solve_rows(Pa, na, tid, Ls, rds);
   else if (tid < 2 * FT && I != J) front_solve_rows(Pb, nb, tid - FT, Ls, rds);
   __syncthreads();
@@ -848,35 +933,65 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
     __threadfence_block();
     if (!front_factor(F, n, s0, lane, d.Frd + s0) && lane == 0) *d.status = 2;
   }
+  if (fwd) {  // forward solve through the panel: z_k, then tile row I's y_i -= L_ik z_k
+    const double v = front_subst(yk, Ls, rds, lane);
+    if (lane < FB) {
+      zs[lane] = v;
+      if (I == 0) d.zF[k0 + lane] = v;
+    }
+    wave_sync();
+    if (lane < nb) {
+      double t = 0.0;
+#pragma unroll
+      for (int k = 0; k < FB; ++k) t += Pb[k * FT + lane] * zs[k];
+      d.yF[s0 + FT * I + lane] = yi - t;
+    }
+  }
 }
 
 // Products of one solve level kept in LDS at a time.
-constexpr int SOLVE_CHUNK = 1024;
+constexpr int SOLVE_CHUNK = 512;
+// Sparse columns whose solution is kept in LDS during the backward solve.
+constexpr int XS_MAX = 1536;
+// Sparse levels whose ranges are kept in LDS during the backward solve.
+constexpr int LV_MAX = 512;
+static_assert(SOLVE_CHUNK >= FIN_WG, "one product per thread in a level's first round");
 
-// One level of a sparse triangular solve, by the workgroup. Forward: for each
-// column c of the level, y_c = L_cc^{-1} (y_c - sum_k L_ck y_k) over its row
-// blocks; backward: x_c = L_cc^{-T} (x_c - sum_i L_ic^T x_i) over its column
-// blocks. Every block product of the level is formed in parallel (one thread per
-// block, into LDS), then one thread per column sums its own products in list order.
-template <bool backward>
-__device__ inline void solve_level(const PgoDev& d, int l, double* prod) {
+// Barrier that orders LDS only: the global loads in flight (the next level's
+// factor data) are not waited for.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// x of a row block's node for the backward solve: the front's part from ys, the
+// sparse columns' from xs when it is kept there, else from g.
+__device__ inline const double* bs_x(const PgoDev& d, int row, const double* xs, const double* ys) {
+  if (row >= d.p0 && d.K > 0) return ys + 7 * (row - d.p0);
+  return xs ? xs + 7 * row : d.g + 7 * row;
+}
+
+// One level of the backward solve L^T x = y over the sparse columns, the general
+// form (any number of blocks and columns): x_c = L_cc^{-T} (y_c - sum_i L_ic^T x_i)
+// over column c's blocks. Every block product of the level is formed in parallel
+// (one thread per block, into LDS), then one thread per column sums its own
+// products in list order. The solution goes to xs when given (else to g).
+__device__ inline void solve_level_bwd(const PgoDev& d, int l, double* prod, double* xs, const double* ys) {
   const int tid = threadIdx.x;
-  const int32_t* ptr = backward ? d.bs_ptr : d.fs_ptr;
-  const int32_t* blk = backward ? d.bs_blk : d.fs_blk;
   const int j0 = d.flev_ptr[l], j1 = d.flev_ptr[l + 1];
   for (int jb = j0; jb < j1; jb += FIN_WG) {
     const int j = jb + tid;
     const bool own = j < j1;
     const int c = own ? d.flev_col[j] : 0;
-    const int p_lo = own ? ptr[j] : 0, p_hi = own ? ptr[j + 1] : 0;
+    const int p_lo = own ? d.bs_ptr[j] : 0, p_hi = own ? d.bs_ptr[j + 1] : 0;
     double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-    const int q_lo = ptr[jb], q_hi = ptr[min(jb + FIN_WG, j1)];
+    const int q_lo = d.bs_ptr[jb], q_hi = d.bs_ptr[min(jb + FIN_WG, j1)];
     for (int base = q_lo; base < q_hi; base += SOLVE_CHUNK) {
       const int top = min(base + SOLVE_CHUNK, q_hi);
       for (int q = base + tid; q < top; q += FIN_WG) {
-        const int b = blk[q];
-        const double* L = d.Lb + 49 * b;
-        const double* x = d.g + 7 * (backward ? d.blk_row[b] : d.blk_col[b]);
+        const double* L = d.Lb + 49 * d.bs_blk[q];
+        const double* x = bs_x(d, d.bs_row[q], xs, ys);
         double xv[7];
 #pragma unroll
         for (int u = 0; u < 7; ++u) xv[u] = x[u];
@@ -884,7 +999,7 @@ __device__ inline void solve_level(const PgoDev& d, int l, double* prod) {
         for (int r = 0; r < 7; ++r) {
           double t = 0.0;
 #pragma unroll
-          for (int u = 0; u < 7; ++u) t += (backward ? L[7 * u + r] : L[7 * r + u]) * xv[u];
+          for (int u = 0; u < 7; ++u) t += L[7 * u + r] * xv[u];
           prod[7 * (q - base) + r] = t;
         }
       }
@@ -900,59 +1015,155 @@ __device__ inline void solve_level(const PgoDev& d, int l, double* prod) {
       double v[7];
 #pragma unroll
       for (int r = 0; r < 7; ++r) v[r] = y[r] - acc[r];
+      double* xo = xs ? xs + 7 * c : y;
 #pragma unroll
       for (int r = 0; r < 7; ++r) {
         double t = 0.0;
-        if constexpr (backward) {
 #pragma unroll
-          for (int k = r; k < 7; ++k) t += Di[7 * k + r] * v[k];
-        } else {
-#pragma unroll
-          for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
-        }
-        y[r] = t;
+        for (int k = r; k < 7; ++k) t += Di[7 * k + r] * v[k];
+        xo[r] = t;
       }
     }
   }
   __syncthreads();
 }
 
+// What thread t reads of a level of the backward solve in its first round: the
+// node of block Q0 + t's row (ok when the block exists), the column at schedule
+// position j0 + t (c and its blocks' range relative to Q0; ok when it exists), and
+// from the level's element-major copy of the factor the block's L, the lower
+// triangle of L_cc^{-1} by rows and y_c (coalesced: lane t reads entry t of each
+// element; whole wavefronts past the level's end read none). Indices past the
+// level's end are clamped to its last entry. None of it depends on the solution:
+// a level's share is loaded while the level before it runs, its indices one level
+// earlier still.
+struct BsIdx {
+  int row, c, pl, ph;
+  bool bok, cok;
+};
+struct BsData {
+  double L[49], Di[28], y[7];
+};
+
+// lv: the level table (LVW entries per level)
+__device__ inline void bs_fetch_idx(const PgoDev& d, const int* lv, int l, int t, BsIdx& s) {
+  const int* e = lv + LVW * l;
+  const int j0 = e[0], j1 = e[1], Q0 = e[2], Q1 = e[3];
+  const int q = Q0 + t, j = j0 + t;
+  const int qc = max(min(q, Q1 - 1), 0), jc = min(j, j1 - 1);
+  s.row = d.bs_row[qc];
+  s.c = d.flev_col[jc];
+  s.pl = d.bs_ptr[jc] - Q0;
+  s.ph = d.bs_ptr[jc + 1] - Q0;
+  s.bok = q < Q1;
+  s.cok = j < j1;
+}
+
+// the level's entries are uniform: the element addresses are formed in scalar
+// registers, and each lane adds only its own offset
+__device__ inline void bs_fetch_L(const PgoDev& d, const int* lv, int l, int t, BsData& x) {
+  const int* e = lv + LVW * l;
+  const int NQ = __builtin_amdgcn_readfirstlane(e[6]);
+  const int w0 = __builtin_amdgcn_readfirstlane(t & ~63), lane = t & 63;
+  if (w0 < NQ) {
+    const double* L = d.bw + __builtin_amdgcn_readfirstlane(e[4]) + w0;
+#pragma unroll
+    for (int k = 0; k < 49; ++k) x.L[k] = L[(size_t)k * NQ + lane];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 49; ++k) x.L[k] = 0.0;
+  }
+}
+
+__device__ inline void bs_fetch_col(const PgoDev& d, const int* lv, int l, int t, BsData& x) {
+  const int* e = lv + LVW * l;
+  const int NJ = __builtin_amdgcn_readfirstlane(e[7]);
+  const int w0 = __builtin_amdgcn_readfirstlane(t & ~63), lane = t & 63;
+  if (w0 < NJ) {
+    const double* C = d.bw + __builtin_amdgcn_readfirstlane(e[5]) + w0;
+#pragma unroll
+    for (int k = 0; k < 28; ++k) x.Di[k] = C[(size_t)k * NJ + lane];
+#pragma unroll
+    for (int r = 0; r < 7; ++r) x.y[r] = C[(size_t)(28 + r) * NJ + lane];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 28; ++k) x.Di[k] = 0.0;
+#pragma unroll
+    for (int r = 0; r < 7; ++r) x.y[r] = 0.0;
+  }
+}
+
+// Workgroups of the solves launch besides the one that solves: those that land on
+// its XCD (workgroups are handed to the XCDs in turn) read what it is about to read
+// (the front's lower triangle and block inverses, the sparse part's backward copy),
+// written from every XCD, into that XCD's L2 while it starts.
+constexpr int FIN_HELPERS = 31;
+
+// Reads this helper's share of [p, p + n) doubles (share h of nh), 16 B per lane,
+// eight loads in flight per lane; the result depends on every load.
+__device__ inline unsigned warm_range(const double* p, size_t n, int h, int nh) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+  const size_t n2 = n / 2, lo = n2 * h / nh, hi = n2 * (h + 1) / nh;
+  unsigned keep = 0;
+  for (size_t i = lo + threadIdx.x; i < hi; i += 8 * FIN_WG) {
+    double2 v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = i + (size_t)u * FIN_WG < hi ? q[i + (size_t)u * FIN_WG] : double2{0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < 8; ++u) keep += (unsigned)__double_as_longlong(v[u].x);
+  }
+  return keep;
+}
+
 // The two triangular solves and the update T <- Exp(dx) T, by one workgroup:
-// forward over the sparse columns level by level, the clique rows' right-hand
-// side, forward and backward through the factored front (its part of the vector
-// in LDS), backward over the sparse columns from the root.
+// forward and backward through the factored front (its part of the vector in
+// LDS), then backward over the sparse columns from the root. A level with at
+// most one block and one column per thread runs from data loaded during the
+// level before, its solution kept in LDS (the barriers between its phases then
+// order LDS only); larger levels, or sparse parts too large for LDS, take the
+// general form.
 __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, double lambda, int lm) {
   __shared__ double sh[FIN_WG / 64 + 1];
   __shared__ double ys[FRONT_MAX];
   __shared__ double red[FB];
   __shared__ double prod[7 * SOLVE_CHUNK];
+  __shared__ double xs_lds[7 * XS_MAX];
+  __shared__ int lv[LVW * LV_MAX];
   const int tid = threadIdx.x;
   if (*d.status != 0) return;
+  if (blockIdx.x != 0) {
+    if (blockIdx.x % 8 == 0) {  // a helper on the solving workgroup's XCD
+      const int h = blockIdx.x / 8 - 1;
+      unsigned keep = 0;
+      if (d.K > 0) {
+        // the front's lower triangle, a column's part below its diagonal at a time
+        const int n = d.nF;
+        for (int c0 = h * 8; c0 < n; c0 += 8 * FIN_HELPERS) {
+          double2 v[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const int c = c0 + u, r2 = c / 2 + (int)threadIdx.x;
+            v[u] = c < n && r2 < n / 2 ? reinterpret_cast<const double2*>(d.F + (size_t)c * n)[r2] : double2{0.0, 0.0};
+          }
+#pragma unroll
+          for (int u = 0; u < 8; ++u) keep += (unsigned)__double_as_longlong(v[u].x);
+        }
+        keep += warm_range(d.Finv, (size_t)n * FB, h, FIN_HELPERS);
+      }
+      if (d.bw) keep += warm_range(d.bw, (size_t)d.bw_size, h, FIN_HELPERS);
+      if (keep == 1u) sh[0] = 0.0;  // keeps the loads; this workgroup's own LDS, never read
+    }
+    return;
+  }
+  const bool lv_on = d.bw && d.nflev <= LV_MAX;
+  if (lv_on)
+    for (int x = tid; x < LVW * d.nflev; x += FIN_WG) lv[x] = d.lv[x];  // read after the front's barriers
   // (the forward solve over the sparse columns ran with their factorisation, k_pgo_level_factor)
   if (d.K > 0) {
     const int n = d.nF, nK = 7 * d.K;
-    // ---- the front rows' right-hand side (k_pgo_clique_updates left it in g), into LDS
-    for (int x = tid; x < n; x += FIN_WG) ys[x] = x < nK ? d.g[7 * d.p0 + x] : 0.0;
+    // ---- the front's forward solve (done panel by panel with its factorisation), into LDS
+    for (int x = tid; x < n; x += FIN_WG) ys[x] = d.zF[x];
     __syncthreads();
-    // ---- forward through the front: y_blk = L_blk^{-1} y_blk, then the rows below
-    for (int k0 = 0; k0 < n; k0 += FB) {
-      if (tid < FB) {
-        const double* Vi = d.Finv + (size_t)(k0 / FB) * FB * FB + tid * FB;
-        double t = 0.0;
-#pragma unroll
-        for (int c = 0; c < FB; ++c) t += Vi[c] * ys[k0 + c];
-        wave_sync();  // the other lanes' reads of ys before this write
-        ys[k0 + tid] = t;
-      }
-      __syncthreads();
-      for (int i = k0 + FB + tid; i < n; i += FIN_WG) {
-        double t = 0.0;
-#pragma unroll
-        for (int c = 0; c < FB; ++c) t += d.F[(size_t)(k0 + c) * n + i] * ys[k0 + c];
-        ys[i] -= t;
-      }
-      __syncthreads();
-    }
     // ---- backward through the front: x_blk = L_blk^{-T} (y_blk - sum of L_ib^T x_i below)
     for (int k0 = n - FB; k0 >= 0; k0 -= FB) {
       {
@@ -979,7 +1190,99 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
     __syncthreads();
   }
   // ---- backward solve L^T x = y over the sparse columns, levels from the root
-  for (int l = d.nflev - 1; l >= 0; --l) solve_level<true>(d, l, prod);
+  double* xs = d.p0 <= XS_MAX ? xs_lds : nullptr;
+  if (d.K == 0) __syncthreads();  // lv (the front's barriers order it otherwise)
+  auto fast = [&](int l) {
+    return lv_on && xs && lv[LVW * l + 1] - lv[LVW * l] <= FIN_WG && lv[LVW * l + 3] - lv[LVW * l + 2] <= FIN_WG;
+  };
+  for (int l = d.nflev - 1; l >= 0;) {
+    if (!fast(l)) {
+      solve_level_bwd(d, l, prod, xs, ys);
+      --l;
+      continue;
+    }
+    // a run of levels that each fit in one round. Two sets of indices take turns
+    // (the loop runs two levels per turn), so that the next level's set is never
+    // copied: a copy would wait for its loads and, the counter of loads in flight
+    // being in order, for the blocks loaded after them.
+    BsIdx ia, ib;
+    BsData sd;
+    bs_fetch_idx(d, lv, l, tid, ia);
+    bs_fetch_L(d, lv, l, tid, sd);
+    bs_fetch_col(d, lv, l, tid, sd);
+    if (l > 0 && fast(l - 1)) bs_fetch_idx(d, lv, l - 1, tid, ib);
+    // one level from cur (its indices), with nxt holding the next level's; cur takes
+    // the indices of the level after next. False when the run ends with this level.
+    auto level = [&](int lc, BsIdx& cur) -> bool {
+      // block phase: this thread's block product L^T x_row
+      if (cur.bok) {
+        const double* x = bs_x(d, cur.row, xs, ys);
+        double xv[7];
+#pragma unroll
+        for (int u = 0; u < 7; ++u) xv[u] = x[u];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int u = 0; u < 7; ++u) t += sd.L[7 * u + r] * xv[u];
+          prod[7 * tid + r] = t;
+        }
+      }
+      const bool more = lc > 0 && fast(lc - 1);
+      if (more) {  // the next level's blocks (L is free once the products are formed)
+        __builtin_amdgcn_sched_barrier(0);
+        bs_fetch_L(d, lv, lc - 1, tid, sd);
+      }
+      lds_barrier();
+      // column phase: x_c = L_cc^{-T} (y_c - sum of the column's products, in list
+      // order; the products are read from LDS three blocks at a time)
+      if (cur.cok) {
+        double acc[7] = {0, 0, 0, 0, 0, 0, 0};
+        int q = cur.pl;
+        for (; q + 3 <= cur.ph; q += 3) {
+          double pv[3][7];
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int r = 0; r < 7; ++r) pv[u][r] = prod[7 * (q + u) + r];
+#pragma unroll
+          for (int u = 0; u < 3; ++u)
+#pragma unroll
+            for (int r = 0; r < 7; ++r) acc[r] += pv[u][r];
+        }
+        for (; q < cur.ph; ++q)
+#pragma unroll
+          for (int r = 0; r < 7; ++r) acc[r] += prod[7 * q + r];
+        double v[7];
+#pragma unroll
+        for (int r = 0; r < 7; ++r) v[r] = sd.y[r] - acc[r];
+        double* xo = xs + 7 * cur.c;
+#pragma unroll
+        for (int r = 0; r < 7; ++r) {
+          double t = 0.0;
+#pragma unroll
+          for (int k = r; k < 7; ++k) t += sd.Di[k * (k + 1) / 2 + r] * v[k];
+          xo[r] = t;
+        }
+      }
+      if (more) {  // the next level's diagonal blocks and y, then the indices of the one after it
+        __builtin_amdgcn_sched_barrier(0);
+        bs_fetch_col(d, lv, lc - 1, tid, sd);
+        if (lc > 1 && fast(lc - 2)) bs_fetch_idx(d, lv, lc - 2, tid, cur);
+      }
+      lds_barrier();
+      return more;
+    };
+    for (;;) {
+      if (!level(l--, ia)) break;
+      if (!level(l--, ib)) break;
+    }
+  }
+  __syncthreads();
+  if (xs) {
+    for (int x = tid; x < 7 * d.p0; x += FIN_WG) d.g[x] = xs[x];
+    __syncthreads();
+  }
   // ---- LM: reduction the quadratic model predicts, dx^T (lambda D dx - g) / 2 (fixed order)
   if (lm) {
     double part2 = 0.0;
@@ -1000,6 +1303,7 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
 struct PgoWorkspace {
   int32_t n_nodes = -1, n_edges = -1, gauge = -1;
   std::vector<int32_t> flev, ct;  // host copies of the sparse levels' column and target ranges (launch sizes)
+  std::vector<int32_t> lvh;       // host copy of the level table
   std::vector<int32_t> ij;  // topology the symbolic analysis was made for
   void* buf = nullptr;
   PgoDev dev{};
@@ -1016,10 +1320,12 @@ namespace {
 
 struct Symbolic {
   int m = 0, nblk = 0, nlev = 0, nflev = 0, K = 0, p0 = 0, nF = 0;
+  bool bw_on = false;
+  int64_t bw_size = 0;
   std::vector<int32_t> pos, node, col_ptr, blk_row, blk_col, dg_ptr, dg_edge, ob_ptr, ob_edge, gv_ptr, gv_edge,
       up_ptr, up_a, up_b, lev_ptr, lev_col, flev_ptr, flev_col, lt_tgt, row_ptr, row_blk,
       chain, chain_lev, dt_tgt, dt_ptr, dup_a, dup_b, fs_ptr, fs_blk, bs_ptr, bs_blk, fu_ptr, fu_a, fu_b, ct_ptr,
-      fz_rc;
+      fz_rc, bs_row, lv;
   std::vector<int8_t> gv_sign;
 };
 
@@ -1230,9 +1536,27 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
   for (int c : S.flev_col) {
     S.fs_blk.insert(S.fs_blk.end(), rows[c].begin(), rows[c].end());
     S.fs_ptr.push_back((int32_t)S.fs_blk.size());
-    for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) S.bs_blk.push_back(b);
+    for (int b = S.col_ptr[c]; b < S.col_ptr[c + 1]; ++b) {
+      S.bs_blk.push_back(b);
+      S.bs_row.push_back(S.blk_row[b]);
+    }
     S.bs_ptr.push_back((int32_t)S.bs_blk.size());
   }
+  // level table; the backward solve's element-major copy of the factor is kept when
+  // the sparse part's solution and the table fit in the solve's LDS
+  S.bw_on = S.p0 <= XS_MAX && S.nflev <= LV_MAX;
+  int64_t off = 0;
+  for (int l = 0; l < S.nflev; ++l) {
+    const int j0 = S.flev_ptr[l], j1 = S.flev_ptr[l + 1];
+    const int Q0 = S.bs_ptr[j0], Q1 = S.bs_ptr[j1];
+    const int NQ = (Q1 - Q0 + 63) / 64 * 64, NJ = (j1 - j0 + 63) / 64 * 64;
+    const int lb = (int)off, dc = (int)(off + 49 * (int64_t)NQ);
+    if (S.bw_on) off += 49 * (int64_t)NQ + 35 * (int64_t)NJ;
+    S.lv.insert(S.lv.end(), {j0, j1, Q0, Q1, S.bw_on ? lb : 0, S.bw_on ? dc : 0, NQ, NJ});
+  }
+  S.bw_size = off;
+  S.bs_blk.push_back(0);  // a valid block and node past the end: the solve's clamped reads
+  S.bs_row.push_back(0);
   // chaining order (breadth-first from the gauge over edges in input order)
   std::vector<std::vector<int>> inc(n);
   for (int k = 0; k < E; ++k) {
@@ -1298,6 +1622,7 @@ namespace {
 // across the chip, the clique one panel per launch, then the rest of the solves and
 // the update in one workgroup.
 hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, const std::vector<int32_t>& ct,
+                            const std::vector<int32_t>& lvh,
                             s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
   hipLaunchKernelGGL(k_pgo_chi2, dim3(1), dim3(PGO_WG), 0, st, d, it);
   if (!update || d.m == 0) return hipGetLastError();
@@ -1310,7 +1635,9 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
       const int g = std::min((ntgt + LEV_WG / 64 - 1) / (LEV_WG / 64), 1024);
       hipLaunchKernelGGL(k_pgo_level_updates, dim3(g), dim3(LEV_WG), 0, st, d, l);
     }
-    hipLaunchKernelGGL(k_pgo_level_factor, dim3(std::min(ncol, 1024)), dim3(LEV_WG), 0, st, d, l);
+    const int32_t* e = lvh.data() + LVW * l;
+    const LevelArg la{e[0], e[2], e[4], e[5], e[6], e[7]};
+    hipLaunchKernelGGL(k_pgo_level_factor, dim3(std::min(ncol, 1024)), dim3(LEV_WG), 0, st, d, l, la);
   }
   if (d.K > 0) {
     hipLaunchKernelGGL(k_pgo_clique_updates, dim3((unsigned)((clique_update_waves(d) + 3) / 4)), dim3(256), 0, st, d);
@@ -1321,7 +1648,7 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
     }
     hipLaunchKernelGGL(k_front_inverse, dim3(1), dim3(64), 0, st, d, d.nF - FB);
   }
-  hipLaunchKernelGGL(k_pgo_finish, dim3(1), dim3(FIN_WG), 0, st, d, T, lambda, lm);
+  hipLaunchKernelGGL(k_pgo_finish, dim3(1 + 8 * FIN_HELPERS), dim3(FIN_WG), 0, st, d, T, lambda, lm);
   return hipGetLastError();
 }
 
@@ -1370,7 +1697,7 @@ int pgo_solve_lm(PgoWorkspace* ws, int* last_hip, int32_t n_nodes, int32_t n_edg
       e = hipMemcpyAsync(ws->T_bak, T, sizeof(s3a_sim3) * n_nodes, hipMemcpyDeviceToDevice, st);
       if (e == hipSuccess) e = launch_fill_zero(reinterpret_cast<uint32_t*>(cur.status), 1, st);
       if (e != hipSuccess) return fail(last_hip, e);
-      if ((e = launch_iteration(cur, ws->flev, ws->ct, T, lam, it, 1, 1, st)) != hipSuccess) return fail(last_hip, e);
+      if ((e = launch_iteration(cur, ws->flev, ws->ct, ws->lvh, T, lam, it, 1, 1, st)) != hipSuccess) return fail(last_hip, e);
       int32_t fst = 0;
       double pred = 0.0;
       e = hipMemcpyAsync(&fst, cur.status, sizeof(int32_t), hipMemcpyDeviceToHost, st);
@@ -1563,7 +1890,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<int32_t>(S.row_ptr.size()) + bytes_of<int32_t>(S.row_blk.size());
     total += bytes_of<int32_t>(S.fs_ptr.size()) + bytes_of<int32_t>(S.fs_blk.size() + 1);
     total += bytes_of<int32_t>(S.fu_ptr.size()) + bytes_of<int32_t>(S.fu_a.size() + 1) * 2;
-    total += bytes_of<int32_t>(S.bs_ptr.size()) + bytes_of<int32_t>(S.bs_blk.size() + 1);
+    total += bytes_of<int32_t>(S.bs_ptr.size()) + bytes_of<int32_t>(S.bs_blk.size() + 1) * 2 +
+             bytes_of<int32_t>(S.lv.size() + LVW) + bytes_of<double>((size_t)S.bw_size + 1);
     total += bytes_of<int32_t>(S.chain.size() + 4) + bytes_of<int32_t>(S.chain_lev.size());
     total += bytes_of<double>(49 * (size_t)m) * 2 + bytes_of<double>(49 * (size_t)nb + 49) + bytes_of<double>(7 * (size_t)m + 7);
     total += bytes_of<double>(49 * (size_t)E + 49) + bytes_of<double>(7 * (size_t)E + 7) + bytes_of<double>(E + 1);
@@ -1573,7 +1901,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     total += bytes_of<s3a_sim3>(n_nodes);
     total += bytes_of<double>(56 * (size_t)E + 56);  // Aw
     total += bytes_of<double>((size_t)S.nF * S.nF + 1) + bytes_of<double>((size_t)S.nF * FB + 1) +
-             bytes_of<double>((size_t)S.nF + 1);  // front, its diagonal blocks' inverses, reciprocal pivots
+             bytes_of<double>((size_t)S.nF + 1) * 3;  // front, its diagonal blocks' inverses, reciprocal pivots,
+                                                      // right-hand side, forward solve
     if (ws->buf) {
       (void)hipStreamSynchronize(st);
       (void)hipFree(ws->buf);
@@ -1629,6 +1958,11 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     int32_t* p_fsb = carve<int32_t>(c, S.fs_blk.size() + 1); put(p_fsb, S.fs_blk); d.fs_blk = p_fsb;
     int32_t* p_bsp = carve<int32_t>(c, S.bs_ptr.size()); put(p_bsp, S.bs_ptr); d.bs_ptr = p_bsp;
     int32_t* p_bsb = carve<int32_t>(c, S.bs_blk.size() + 1); put(p_bsb, S.bs_blk); d.bs_blk = p_bsb;
+    int32_t* p_bsr = carve<int32_t>(c, S.bs_row.size() + 1); put(p_bsr, S.bs_row); d.bs_row = p_bsr;
+    int32_t* p_lv = carve<int32_t>(c, S.lv.size() + LVW); put(p_lv, S.lv); d.lv = p_lv;
+    d.bw = carve<double>(c, (size_t)S.bw_size + 1);
+    d.bw_size = S.bw_size;
+    if (!S.bw_on) d.bw = nullptr;
     int32_t* p_ch = carve<int32_t>(c, S.chain.size() + 4); put(p_ch, S.chain); d.chain = p_ch;
     d.n_chain = (int32_t)(S.chain.size() / 4);
     int32_t* p_cl = carve<int32_t>(c, S.chain_lev.size()); put(p_cl, S.chain_lev); d.chain_lev = p_cl;
@@ -1653,6 +1987,8 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     d.F = carve<double>(c, (size_t)S.nF * S.nF + 1);
     d.Finv = carve<double>(c, (size_t)S.nF * FB + 1);
     d.Frd = carve<double>(c, (size_t)S.nF + 1);
+    d.yF = carve<double>(c, (size_t)S.nF + 1);
+    d.zF = carve<double>(c, (size_t)S.nF + 1);
     for (auto& u : up) {
       e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return fail(last_hip, e);
@@ -1671,6 +2007,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
     ws->cap_iters = iters_cap;
     ws->flev = S.flev_ptr;
     ws->ct = S.ct_ptr;
+    ws->lvh = S.lv;
     ws->nnz_blocks = (int64_t)nb + m;
   }
   PgoDev d = ws->dev;
@@ -1687,7 +2024,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
       if ((e = launch_linearize(d, T_meas, omega, T, p.huber_delta, !update, st)) != hipSuccess) return fail(last_hip, e);
     }
     if (update && d.m == 0) continue;
-    if ((e = launch_iteration(d, ws->flev, ws->ct, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
+    if ((e = launch_iteration(d, ws->flev, ws->ct, ws->lvh, T, p.lambda, it, update, 0, st)) != hipSuccess) return fail(last_hip, e);
   }
   if (report) {
     std::vector<double> chi(p.iters + 1, 0.0);
