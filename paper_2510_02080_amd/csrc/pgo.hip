@@ -670,16 +670,18 @@ __shared__ double front_cb[2 * (FB + 1)];
 // square root (hardware estimate, two Newton steps), no division, no inverse.
 constexpr int FRONT_TWG = 256;
 
-// (1) on the chain: the FB x FB diagonal block at (kd, kd) factored in place by
-// one wavefront (lane = row, right-looking: the pivot is read from its lane,
-// each updated column goes to LDS one step before it is needed); 1 / L_jj to
-// rd. False (in every lane) if a pivot is not positive.
-__device__ __attribute__((always_inline)) inline bool front_factor(double* F, int n, int kd, int lane, double* rd) {
+// (1) on the chain: the FB x FB diagonal block at (kd, kd) factored by one
+// wavefront (lane = row, right-looking: the pivot is read from its lane, each
+// updated column goes to LDS one step before it is needed) from src (element
+// (i, c) at src[c * ld + i]: the block in F, or a copy in LDS) into F; 1 / L_jj
+// to rd. False (in every lane) if a pivot is not positive.
+__device__ __attribute__((always_inline)) inline bool front_factor(const double* src, int ld, double* F, int n, int kd,
+                                                                  int lane, double* rd) {
   double* cb = front_cb;
   const int r = lane < FB ? lane : FB - 1, e = lane < FB ? lane : FB;
   double a[FB];  // row r; entries above the diagonal carry values that are never read
 #pragma unroll
-  for (int c = 0; c < FB; ++c) a[c] = F[(size_t)(kd + c) * n + kd + (c <= r ? r : c)];
+  for (int c = 0; c < FB; ++c) a[c] = src[(size_t)c * ld + (c <= r ? r : c)];
   bool ok = true;
   double rv = 1.0;
   cb[e] = a[0];
@@ -775,7 +777,9 @@ __global__ __launch_bounds__(64) void k_front_inverse(PgoDev d, int kd) {
 
 __global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
   if (*d.status != 0) return;
-  if (!front_factor(d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd) && threadIdx.x == 0) *d.status = 2;
+  if (!front_factor(d.F + (size_t)kd * d.nF + kd, d.nF, d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd) &&
+      threadIdx.x == 0)
+    *d.status = 2;
 }
 
 // Rows i < nrow of P (by column: P[k * FT + i], row i of the panel's columns
@@ -825,6 +829,7 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
   __shared__ double Ls[FB * (FB + 1)];         // L_kk by column, strictly lower: Ls[c * (FB + 1) + i]
   __shared__ double rds[FB];
   __shared__ double zs[FB];  // the panel's block of the forward solve
+  __shared__ double Db[FB * (FB + 1)];  // tile (0, 0): the next diagonal block, updated, by column
   if (*d.status != 0) return;
   const int n = d.nF, s0 = k0 + FB, nr = n - s0;
   const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
@@ -846,6 +851,21 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
     if (lane < FB) yk = d.yF[k0 + lane];
     if (lane < nb) yi = d.yF[s0 + FT * I + lane];
   }
+  // this wavefront's quadrant of the tile (row half qi, column half qj), read now:
+  // its latency overlaps the panel's loads and solve
+  const int qi = wv & 1, qj = wv >> 1;
+  d4 acc[2][2];
+  bool live[2][2];
+#pragma unroll
+  for (int cj = 0; cj < 2; ++cj)
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const int ib = FT * I + 32 * qi + 16 * ri, jb = FT * J + 32 * qj + 16 * cj;
+      live[cj][ri] = ib < nr && jb < nr && (I != J || ib >= jb);
+      const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
+    }
   {  // every load issued before any is used (rows past the front's end read the next
      // column's top, in bounds since the panel is not the last, and are zeroed)
     constexpr int NL = FB * FB / FRONT_TWG, NP = FB * FT / FRONT_TWG;
@@ -891,19 +911,6 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
       if (i < nb) F[(size_t)(k0 + k) * n + s0 + FT * I + i] = Pb[x];
     }
   }
-  const int qi = wv & 1, qj = wv >> 1;  // this wavefront's quadrant: row half qi, column half qj
-  d4 acc[2][2];
-  bool live[2][2];
-#pragma unroll
-  for (int cj = 0; cj < 2; ++cj)
-#pragma unroll
-    for (int ri = 0; ri < 2; ++ri) {
-      const int ib = FT * I + 32 * qi + 16 * ri, jb = FT * J + 32 * qj + 16 * cj;
-      live[cj][ri] = ib < nr && jb < nr && (I != J || ib >= jb);
-      const double* src = live[cj][ri] ? F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16 : F;
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[cj][ri][v] = src[live[cj][ri] ? (size_t)(4 * v) * n : 0];
-    }
 #pragma unroll
   for (int k = 0; k < FB; k += 4) {
     double pa[2], pb[2];
@@ -918,20 +925,26 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
       for (int ri = 0; ri < 2; ++ri)
         if (live[cj][ri]) acc[cj][ri] = __builtin_amdgcn_mfma_f64_16x16x4f64(pa[cj], pb[ri], acc[cj][ri], 0, 0, 0);
   }
+  const bool next_diag = ti == 0 && wv == 0;  // quadrant (0, 0) of tile (0, 0): the next diagonal block
 #pragma unroll
   for (int cj = 0; cj < 2; ++cj)
 #pragma unroll
     for (int ri = 0; ri < 2; ++ri) {
       if (!live[cj][ri]) continue;
       const int ib = FT * I + 32 * qi + 16 * ri, jb = FT * J + 32 * qj + 16 * cj;
+      if (next_diag) {  // to LDS for the factor, which writes the block to F
+#pragma unroll
+        for (int v = 0; v < 4; ++v) Db[(jb + l4 + 4 * v) * (FB + 1) + ib + l16] = acc[cj][ri][v];
+        continue;
+      }
       double* dst = F + (size_t)(s0 + jb + l4) * n + s0 + ib + l16;
 #pragma unroll
       for (int v = 0; v < 4; ++v)
         if (ib != jb || ib + l16 >= jb + l4 + 4 * v) dst[(size_t)(4 * v) * n] = acc[cj][ri][v];
     }
-  if (ti == 0 && wv == 0 && s0 < n) {  // the next diagonal block: quadrant (0, 0) of tile (0, 0), just stored
-    __threadfence_block();
-    if (!front_factor(F, n, s0, lane, d.Frd + s0) && lane == 0) *d.status = 2;
+  if (next_diag) {
+    wave_sync();
+    if (!front_factor(Db, FB + 1, F, n, s0, lane, d.Frd + s0) && lane == 0) *d.status = 2;
   }
   if (fwd) {  // forward solve through the panel: z_k, then tile row I's y_i -= L_ik z_k
     const double v = front_subst(yk, Ls, rds, lane);
