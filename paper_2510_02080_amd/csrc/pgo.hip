@@ -16,9 +16,10 @@
 // Device, per iteration: the edges are linearised and H and g assembled across
 // the chip; the sparse columns are factored level by level, two launches per
 // level spread over the chip (the columns of a level are independent), each
-// column's forward solve with its factor; the dense trailing clique is factored
-// one panel per launch, its tiles across the chip on the matrix cores; one
-// workgroup finishes the solves of L L^T dx = -g and applies T <- Exp(dx) T.
+// column's forward solve with its factor; the dense front (the trailing clique
+// and the columns that fit in its padding) is factored one panel per launch, its
+// tiles across the chip on the matrix cores, with its forward solve; one
+// workgroup runs the backward solves of L L^T dx = -g and applies T <- Exp(dx) T.
 #include <string.h>
 
 #include <algorithm>
@@ -1631,9 +1632,9 @@ namespace {
 
 // One damped solve and update of the poses (or, without update, only chi^2 at the
 // current linearisation): assembly across the chip, the sparse factorisation and
-// forward solve level by level across the chip, the clique's sparse-column updates
-// across the chip, the clique one panel per launch, then the rest of the solves and
-// the update in one workgroup.
+// forward solve level by level across the chip, the front's sparse-column updates
+// and right-hand side across the chip, the front and its forward solve one panel
+// per launch, then the backward solves and the update in one workgroup.
 hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, const std::vector<int32_t>& ct,
                             const std::vector<int32_t>& lvh,
                             s3a_sim3* T, double lambda, int it, int update, int lm, hipStream_t st) {
