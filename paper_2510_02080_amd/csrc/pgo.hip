@@ -665,10 +665,11 @@ __shared__ double front_cb[2 * (FB + 1)];
 //                   rows it needs and updates its tile on the matrix cores; the
 //                   workgroup of the leading tile then factors the next diagonal
 //                   block, and one more workgroup inverts panel k0's diagonal
-//                   block for the solves (front_inverse), off the chain;
-//   k_front_inverse the last diagonal block's inverse.
-// Only the factor of each diagonal block is on the chain: pivots by reciprocal
-// square root (hardware estimate, two Newton steps), no division, no inverse.
+//                   block for the backward solve (front_inverse), off the chain.
+// The last diagonal block is solved by substitution in the solves kernel, so no
+// inverse is formed on the chain. Only the factor of each diagonal block is on
+// the chain: pivots by reciprocal square root (hardware estimate, two Newton
+// steps), no division.
 constexpr int FRONT_TWG = 256;
 
 // (1) on the chain: the FB x FB diagonal block at (kd, kd) factored by one
@@ -762,19 +763,6 @@ __device__ inline double front_subst(double v, const double* Ls, const double* r
   return v;
 }
 
-// The last diagonal block: its inverse (for the backward solve) and the last
-// block of the forward solve, z = L_kk^{-1} y.
-__global__ __launch_bounds__(64) void k_front_inverse(PgoDev d, int kd) {
-  __shared__ double Ls[FB * (FB + 1)];
-  __shared__ double rds[FB];
-  if (*d.status != 0) return;
-  const int lane = (int)threadIdx.x;
-  front_inverse(d.F, d.nF, kd, lane, d.Frd + kd, d.Finv + (size_t)(kd / FB) * FB * FB, Ls);
-  if (lane < FB) rds[lane] = d.Frd[kd + lane];
-  wave_sync();
-  const double v = front_subst(lane < FB ? d.yF[kd + lane] : 0.0, Ls, rds, lane);
-  if (lane < FB) d.zF[kd + lane] = v;
-}
 
 __global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
   if (*d.status != 0) return;
@@ -1178,8 +1166,30 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
     // ---- the front's forward solve (done panel by panel with its factorisation), into LDS
     for (int x = tid; x < n; x += FIN_WG) ys[x] = d.zF[x];
     __syncthreads();
+    // ---- its last diagonal block, forward and backward by substitution (one wavefront,
+    // the block by column in prod, 1 / L_jj in red): z = L^{-1} y, then x = L^{-T} z
+    const int kl = n - FB;
+    if (tid < 64) {
+      const int lane = tid;
+      double* lt = prod;
+      for (int x = lane; x < FB * FB; x += 64) {
+        const int c = x / FB, i = x % FB;
+        lt[c * (FB + 1) + i] = i > c ? d.F[(size_t)(kl + c) * n + kl + i] : 0.0;
+      }
+      if (lane < FB) red[lane] = d.Frd[kl + lane];
+      wave_sync();
+      double v = front_subst(lane < FB ? d.yF[kl + lane] : 0.0, lt, red, lane);
+#pragma unroll
+      for (int k = FB - 1; k >= 0; --k) {
+        const double xk = readlane_f64(v, k) * red[k];
+        if (lane < k) v -= lt[lane * (FB + 1) + k] * xk;
+        v = lane == k ? xk : v;
+      }
+      if (lane < FB) ys[kl + lane] = v;
+    }
+    __syncthreads();
     // ---- backward through the front: x_blk = L_blk^{-T} (y_blk - sum of L_ib^T x_i below)
-    for (int k0 = n - FB; k0 >= 0; k0 -= FB) {
+    for (int k0 = kl - FB; k0 >= 0; k0 -= FB) {
       {
         constexpr int SL = FIN_WG / FB;  // row slots per column
         const int c = tid / SL, q = tid % SL;
@@ -1660,7 +1670,6 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
       const int nr = d.nF - k0 - FB, T = (nr + FT - 1) / FT;
       hipLaunchKernelGGL(k_front_update, dim3(T * (T + 1) / 2 + 1), dim3(FRONT_TWG), 0, st, d, k0);
     }
-    hipLaunchKernelGGL(k_front_inverse, dim3(1), dim3(64), 0, st, d, d.nF - FB);
   }
   hipLaunchKernelGGL(k_pgo_finish, dim3(1 + 8 * FIN_HELPERS), dim3(FIN_WG), 0, st, d, T, lambda, lm);
   return hipGetLastError();
