@@ -1047,11 +1047,16 @@ struct BsData {
   double L[49], Di[28], y[7];
 };
 
+// A level with few columns takes one wavefront per column (its lanes share the
+// column's sums), others one thread per column.
+constexpr int BS_WIDE = FIN_WG / 64;
+__device__ inline bool bs_wide(const int* lv, int l) { return lv[LVW * l + 1] - lv[LVW * l] <= BS_WIDE; }
+
 // lv: the level table (LVW entries per level)
 __device__ inline void bs_fetch_idx(const PgoDev& d, const int* lv, int l, int t, BsIdx& s) {
   const int* e = lv + LVW * l;
   const int j0 = e[0], j1 = e[1], Q0 = e[2], Q1 = e[3];
-  const int q = Q0 + t, j = j0 + t;
+  const int q = Q0 + t, j = j0 + (bs_wide(lv, l) ? t >> 6 : t);
   const int qc = max(min(q, Q1 - 1), 0), jc = min(j, j1 - 1);
   s.row = d.bs_row[qc];
   s.c = d.flev_col[jc];
@@ -1080,13 +1085,16 @@ __device__ inline void bs_fetch_L(const PgoDev& d, const int* lv, int l, int t, 
 __device__ inline void bs_fetch_col(const PgoDev& d, const int* lv, int l, int t, BsData& x) {
   const int* e = lv + LVW * l;
   const int NJ = __builtin_amdgcn_readfirstlane(e[7]);
+  const bool wide = bs_wide(lv, l);
   const int w0 = __builtin_amdgcn_readfirstlane(t & ~63), lane = t & 63;
-  if (w0 < NJ) {
-    const double* C = d.bw + __builtin_amdgcn_readfirstlane(e[5]) + w0;
+  // the column of this thread: its wavefront's (every lane the same) or its own
+  const int base = wide ? w0 >> 6 : w0, off = wide ? 0 : lane;
+  if ((wide ? (w0 >> 6) < e[1] - e[0] : w0 < NJ)) {
+    const double* C = d.bw + __builtin_amdgcn_readfirstlane(e[5]) + base;
 #pragma unroll
-    for (int k = 0; k < 28; ++k) x.Di[k] = C[(size_t)k * NJ + lane];
+    for (int k = 0; k < 28; ++k) x.Di[k] = C[(size_t)k * NJ + off];
 #pragma unroll
-    for (int r = 0; r < 7; ++r) x.y[r] = C[(size_t)(28 + r) * NJ + lane];
+    for (int r = 0; r < 7; ++r) x.y[r] = C[(size_t)(28 + r) * NJ + off];
   } else {
 #pragma unroll
     for (int k = 0; k < 28; ++k) x.Di[k] = 0.0;
@@ -1258,35 +1266,47 @@ __global__ __launch_bounds__(FIN_WG) void k_pgo_finish(PgoDev d, s3a_sim3* T, do
         bs_fetch_L(d, lv, lc - 1, tid, sd);
       }
       lds_barrier();
-      // column phase: x_c = L_cc^{-T} (y_c - sum of the column's products, in list
-      // order; the products are read from LDS three blocks at a time)
+      // column phase: x_c = L_cc^{-T} (y_c - sum of the column's products). One thread
+      // per column sums in list order, three blocks' products read at a time; with
+      // few columns a wavefront per column sums lane-strided partials and reduces
+      // them with the fixed DPP tree.
+      const bool wide = bs_wide(lv, lc);
       if (cur.cok) {
         double acc[7] = {0, 0, 0, 0, 0, 0, 0};
-        int q = cur.pl;
-        for (; q + 3 <= cur.ph; q += 3) {
-          double pv[3][7];
+        if (wide) {
+          for (int q = cur.pl + (tid & 63); q < cur.ph; q += 64)
 #pragma unroll
-          for (int u = 0; u < 3; ++u)
+            for (int r = 0; r < 7; ++r) acc[r] += prod[7 * q + r];
+          wave_totals_f64(acc);
+        } else {
+          int q = cur.pl;
+          for (; q + 3 <= cur.ph; q += 3) {
+            double pv[3][7];
 #pragma unroll
-            for (int r = 0; r < 7; ++r) pv[u][r] = prod[7 * (q + u) + r];
+            for (int u = 0; u < 3; ++u)
 #pragma unroll
-          for (int u = 0; u < 3; ++u)
+              for (int r = 0; r < 7; ++r) pv[u][r] = prod[7 * (q + u) + r];
 #pragma unroll
-            for (int r = 0; r < 7; ++r) acc[r] += pv[u][r];
+            for (int u = 0; u < 3; ++u)
+#pragma unroll
+              for (int r = 0; r < 7; ++r) acc[r] += pv[u][r];
+          }
+          for (; q < cur.ph; ++q)
+#pragma unroll
+            for (int r = 0; r < 7; ++r) acc[r] += prod[7 * q + r];
         }
-        for (; q < cur.ph; ++q)
-#pragma unroll
-          for (int r = 0; r < 7; ++r) acc[r] += prod[7 * q + r];
         double v[7];
 #pragma unroll
         for (int r = 0; r < 7; ++r) v[r] = sd.y[r] - acc[r];
-        double* xo = xs + 7 * cur.c;
+        if (!wide || (tid & 63) == 0) {
+          double* xo = xs + 7 * cur.c;
 #pragma unroll
-        for (int r = 0; r < 7; ++r) {
-          double t = 0.0;
+          for (int r = 0; r < 7; ++r) {
+            double t = 0.0;
 #pragma unroll
-          for (int k = r; k < 7; ++k) t += sd.Di[k * (k + 1) / 2 + r] * v[k];
-          xo[r] = t;
+            for (int k = r; k < 7; ++k) t += sd.Di[k * (k + 1) / 2 + r] * v[k];
+            xo[r] = t;
+          }
         }
       }
       if (more) {  // the next level's diagonal blocks and y, then the indices of the one after it
