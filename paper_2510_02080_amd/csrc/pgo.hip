@@ -500,6 +500,7 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
   if (*d.status != 0) return;
   __shared__ int s_fail;
   __shared__ double part[LEV_WG / 64][7];
+  __shared__ double sDi[49];  // L_cc^{-1}: read by the forward solve and the panel rows from LDS
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   for (int j = d.flev_ptr[l] + (int)blockIdx.x; j < d.flev_ptr[l + 1]; j += (int)gridDim.x) {
     const int col = d.flev_col[j];
@@ -507,7 +508,7 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
     // coalesced read per element for a level's columns and blocks)
     const int pj = j - la.j0, NJ = la.NJ;
     double* bwc = d.bw ? d.bw + la.dc + pj : nullptr;
-    if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, d.Di + 49 * col, bwc, NJ) ? 0 : 1;
+    if (threadIdx.x == 0) s_fail = chol7_lane(d.Ld + 49 * col, sDi, bwc, NJ) ? 0 : 1;
     // forward solve of this column, y_c = L_cc^{-1} (y_c - sum_k L_ck y_k): its row blocks
     // (c, k) lie in factored columns of lower levels, whose y_k are final; per-thread
     // sums over the blocks (strided), then a fixed tree
@@ -533,6 +534,7 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
       if (threadIdx.x == 0) *d.status = 2;
       return;
     }
+    if (threadIdx.x >= 64 && threadIdx.x < 64 + 49) d.Di[49 * col + threadIdx.x - 64] = sDi[threadIdx.x - 64];
     if (threadIdx.x == 0) {
       double v[7];
 #pragma unroll
@@ -542,12 +544,11 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
         for (int q = 0; q < LEV_WG / 64; ++q) s += part[q][r];
         v[r] = d.g[7 * col + r] - s;
       }
-      const double* Di = d.Di + 49 * col;
 #pragma unroll
       for (int r = 0; r < 7; ++r) {
         double t = 0.0;
 #pragma unroll
-        for (int k = 0; k <= r; ++k) t += Di[7 * r + k] * v[k];
+        for (int k = 0; k <= r; ++k) t += sDi[7 * r + k] * v[k];
         d.g[7 * col + r] = t;
         if (bwc) bwc[(28 + r) * NJ] = t;
       }
@@ -555,7 +556,7 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
     const int b0 = d.col_ptr[col], nb = d.col_ptr[col + 1] - b0;
     const int pq = d.bs_ptr[j] - la.Q0, NQ = la.NQ;
     for (int x = (int)threadIdx.x; x < 7 * nb; x += LEV_WG)
-      trsm_row(d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7), d.Di + 49 * col,
+      trsm_row(d.Lb + 49 * (b0 + x / 7) + 7 * (x % 7), sDi,
                d.bw ? d.bw + la.lb + 7 * (x % 7) * NQ + pq + x / 7 : nullptr, NQ);
     __syncthreads();
   }
