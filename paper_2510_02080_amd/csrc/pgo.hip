@@ -94,7 +94,7 @@ struct PgoDev {
   double* Frd;    // [nF] 1 / L_jj of the front's factor
   double* yF;     // [nF] the front's right-hand side, updated panel by panel by the forward solve
   double* zF;     // [nF] the front's forward solve L_F z = y, block by block
-  // rows of L: blocks (c, k), k < c (the clique rows' right-hand side)
+  // rows of L: blocks (c, k), k < c (the front rows' right-hand side)
   const int32_t* row_ptr; const int32_t* row_blk;
   // chaining order: (node, parent, edge, dir) for nodes reached by breadth-first search
   const int32_t* chain; int32_t n_chain;
@@ -301,7 +301,7 @@ __device__ inline double wg_sum(double v, double* sh) {
   return s;
 }
 
-// Dense front of the trailing clique: at most PGO_KMAX node columns; panels of FB
+// Dense front of the trailing columns: at most PGO_KMAX node columns; panels of FB
 // columns, trailing updates in FT x FT tiles.
 constexpr int PGO_KMAX = 73;
 constexpr int FB = 32;
@@ -1547,7 +1547,7 @@ Symbolic analyse(int n, int E, const int32_t* ij, int gauge) {
     S.flev_ptr.push_back((int32_t)S.flev_col.size());
   }
   S.nflev = (int)S.flev_ptr.size() - 1;
-  // the clique: block map, and each of its targets' updates from sparse columns
+  // the front: block map, and each of its targets' updates from sparse columns
   S.dt_ptr.assign(1, 0);
   for (int c = p0; c < m; ++c) {
     std::vector<int> tg{c};
@@ -2037,7 +2037,7 @@ int pgo_solve(PgoWorkspace** wsp, int* last_hip, int32_t n_nodes, int32_t n_edge
       e = hipMemcpyAsync(u.first, u.second.first, u.second.second, hipMemcpyHostToDevice, st);
       if (e != hipSuccess) return fail(last_hip, e);
     }
-    if (d.nF > 0) {  // identity padding of the front; the clique's part is rewritten every iteration
+    if (d.nF > 0) {  // identity padding of the front; its lower triangle is rewritten every iteration
       const size_t nn = (size_t)d.nF * d.nF;
       hipLaunchKernelGGL(k_pgo_front_init, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, st, d);
       if ((e = hipGetLastError()) != hipSuccess) return fail(last_hip, e);
