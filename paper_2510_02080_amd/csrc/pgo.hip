@@ -13,6 +13,12 @@
 // symbolic block Cholesky (column structures, elimination tree, levels), and
 // fixed-order lists: which edges assemble into which block, and which pairs of
 // factor blocks update which target block.
+// A failed factorisation (a pivot not positive) sets the solve's status. The
+// kernels of the linearisation, the factorisation and the front run whatever the
+// status (all they write is workspace, rewritten in full by the next iteration or
+// trial; reading the status first would put a dependent load at the head of each
+// launch); the chi^2 sum and the solves kernel, which write what the caller
+// reads, check it.
 // Device, per iteration: the edges are linearised and H and g assembled across
 // the chip; the sparse columns are factored level by level, two launches per
 // level spread over the chip (the columns of a level are independent), each
@@ -435,7 +441,6 @@ __device__ inline void trsm_row(double* row, const double* Dinv, double* copy, i
 // Assembly of the normal equations from the per-edge linearisations:
 // independent sums, spread over the whole chip.
 __global__ __launch_bounds__(256) void k_pgo_assemble(PgoDev d, double lambda, int lm) {
-  if (*d.status != 0) return;
   const int gt = blockIdx.x * blockDim.x + threadIdx.x, gs = gridDim.x * blockDim.x;
   // ---- assembly (diagonal blocks, off-diagonal blocks, gradient)
   for (int x = gt; x < d.m * 49; x += gs) {
@@ -483,12 +488,12 @@ constexpr int LEV_WG = 256;
 constexpr int LVW = 8;  // entries per level of the level table
 // A level's entries of the table, passed to its factor launch by value.
 struct LevelArg {
-  int j0, Q0, lb, dc, NQ, NJ;
+  int j0, j1, Q0, lb, dc, NQ, NJ;
 };
-__global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
-  if (*d.status != 0) return;
+// (The level's ranges come from the host as arguments: read from the index lists
+// they would be a chain of dependent loads before any work.)
+__global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int i0, int i1) {
   const int lane = threadIdx.x & 63;
-  const int i0 = d.ct_ptr[d.flev_ptr[l]], i1 = d.ct_ptr[d.flev_ptr[l + 1]];
   const int waves = (int)gridDim.x * (LEV_WG / 64);
   for (int i = i0 + (int)blockIdx.x * (LEV_WG / 64) + ((int)threadIdx.x >> 6); i < i1; i += waves) {
     double* e = target_elem(d, d.lt_tgt[i], lane);
@@ -497,12 +502,11 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_updates(PgoDev d, int l) {
 }
 
 __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, LevelArg la) {
-  if (*d.status != 0) return;
   __shared__ int s_fail;
   __shared__ double part[LEV_WG / 64][7];
   __shared__ double sDi[49];  // L_cc^{-1}: read by the forward solve and the panel rows from LDS
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  for (int j = d.flev_ptr[l] + (int)blockIdx.x; j < d.flev_ptr[l + 1]; j += (int)gridDim.x) {
+  for (int j = la.j0 + (int)blockIdx.x; j < la.j1; j += (int)gridDim.x) {
     const int col = d.flev_col[j];
     // the backward solve's copy of this column (level-major, element-major: one
     // coalesced read per element for a level's columns and blocks)
@@ -572,7 +576,6 @@ __global__ __launch_bounds__(LEV_WG) void k_pgo_level_factor(PgoDev d, int l, Le
 //   [.., + pad waves)      the padding rows' lower entries, identity (and their
 //                          right-hand side, zero).
 __global__ __launch_bounds__(256) void k_pgo_clique_updates(PgoDev d) {
-  if (*d.status != 0) return;
   int ti = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   const int r = lane < 49 ? lane / 7 : 0, s = lane < 49 ? lane % 7 : 0;
@@ -766,7 +769,6 @@ __device__ inline double front_subst(double v, const double* Ls, const double* r
 
 
 __global__ __launch_bounds__(64) void k_front_diag(PgoDev d, int kd) {
-  if (*d.status != 0) return;
   if (!front_factor(d.F + (size_t)kd * d.nF + kd, d.nF, d.F, d.nF, kd, (int)threadIdx.x, d.Frd + kd) &&
       threadIdx.x == 0)
     *d.status = 2;
@@ -820,7 +822,6 @@ __global__ __launch_bounds__(FRONT_TWG) void k_front_update(PgoDev d, int k0) {
   __shared__ double rds[FB];
   __shared__ double zs[FB];  // the panel's block of the forward solve
   __shared__ double Db[FB * (FB + 1)];  // tile (0, 0): the next diagonal block, updated, by column
-  if (*d.status != 0) return;
   const int n = d.nF, s0 = k0 + FB, nr = n - s0;
   const int T = (nr + FT - 1) / FT, ntile = T * (T + 1) / 2;
   const int ti = (int)blockIdx.x, tid = (int)threadIdx.x;
@@ -1678,10 +1679,10 @@ hipError_t launch_iteration(const PgoDev& d, const std::vector<int32_t>& flev, c
     const int ntgt = ct[flev[l + 1]] - ct[flev[l]], ncol = flev[l + 1] - flev[l];
     if (ntgt > 0) {
       const int g = std::min((ntgt + LEV_WG / 64 - 1) / (LEV_WG / 64), 1024);
-      hipLaunchKernelGGL(k_pgo_level_updates, dim3(g), dim3(LEV_WG), 0, st, d, l);
+      hipLaunchKernelGGL(k_pgo_level_updates, dim3(g), dim3(LEV_WG), 0, st, d, ct[flev[l]], ct[flev[l + 1]]);
     }
     const int32_t* e = lvh.data() + LVW * l;
-    const LevelArg la{e[0], e[2], e[4], e[5], e[6], e[7]};
+    const LevelArg la{e[0], e[1], e[2], e[4], e[5], e[6], e[7]};
     hipLaunchKernelGGL(k_pgo_level_factor, dim3(std::min(ncol, 1024)), dim3(LEV_WG), 0, st, d, l, la);
   }
   if (d.K > 0) {
